@@ -1,0 +1,297 @@
+"""Pins of the CPU oracle against what the mathematics fixes (no GPU).
+
+Each pin is independent of the oracle's own code: exact rational arithmetic
+checked by Z X = I and the Leibniz determinant, a 200-bit mpmath library
+routine, LAPACK through numpy, closed forms (identity, diagonal, scaling,
+the stored worked example) and the Wishart closed forms at S = Z and S = aZ.
+"""
+import itertools
+import json
+import math
+import os
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact
+from paper_1807_08084_amd import synth
+
+U64 = 2.0 ** -53
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_example.json")
+
+
+def hpd(rng, m, eig):
+    """m Haar-rotated Hermitian matrices with eigenvalues eig (m, 3); (9, m)."""
+    U = synth.haar_unitary(rng, m)
+    Z = np.einsum("mij,mj,mkj->mik", U, eig, np.conj(U))
+    return synth.pack(Z)
+
+
+def random_hpd(rng, m, kmax_log10):
+    lg = rng.uniform(0.0, kmax_log10, size=(m, 1))
+    mid = rng.uniform(0.0, 1.0, size=(m, 1))
+    eig = np.concatenate([np.ones((m, 1)), 10.0 ** (-lg * mid), 10.0 ** (-lg)], axis=1)
+    return hpd(rng, m, eig), np.maximum(eig[:, 0] / eig[:, 2], 1.0)
+
+
+# --------------------------------------------------------------- golden
+def test_worked_example_exact_and_oracles():
+    g = json.load(open(GOLDEN))
+    z = np.array(g["z"], dtype=np.float64)[:, None]
+    inv_ref = np.array([float(F(s)) for s in g["inverse"]])[:, None]
+    det_ref = float(F(g["det"]))
+    # the stored values are reproduced by the exact brute force
+    X, det = exact.inv_det(exact.unpack(g["z"]))
+    assert [str(v) for v in exact.pack(X)] == g["inverse"] and str(det.re) == g["det"]
+    # adjugate = det * inverse, as stored
+    adj = [F(s) for s in g["adjugate"]]
+    assert all(a == F(x) * F(g["det"]) for a, x in zip(adj, g["inverse"]))
+    for inv, d in (oracle.ge(z), oracle.chol(z)):
+        assert np.abs(inv - inv_ref).max() <= 4 * U64 * np.abs(inv_ref).max()
+        assert abs(d[0] - det_ref) <= 8 * U64 * det_ref
+    for (ih, il), (dh, dl) in (oracle.ge128(z), oracle.chol128(z)):
+        assert np.array_equal(ih, inv_ref)  # exact fractions with short binary expansions round to themselves
+        assert dh[0] == det_ref
+
+
+# --------------------------------------------------------------- exact brute force
+def _leibniz(A):
+    tot = exact.Q(0)
+    for perm in itertools.permutations(range(3)):
+        sgn = 1
+        for i in range(3):
+            for j in range(i + 1, 3):
+                if perm[i] > perm[j]:
+                    sgn = -sgn
+        term = exact.Q(sgn)
+        for i in range(3):
+            term = term * A[i][perm[i]]
+        tot = tot + term
+    return tot
+
+
+def test_exact_brute_force_is_the_inverse():
+    """Pin of the exact oracle itself: Z X = I and det = Leibniz, exactly."""
+    rng = np.random.default_rng(11)
+    for _ in range(60):
+        p = list(rng.integers(-3, 4, size=9))
+        p[0], p[1], p[2] = (int(x) for x in rng.integers(1, 9, size=3))
+        A = exact.unpack(p)
+        X, det = exact.inv_det(A)
+        assert det == _leibniz(A)
+        if X is None:
+            continue
+        for i in range(3):
+            for j in range(3):
+                s = exact.Q(0)
+                for k in range(3):
+                    s = s + A[i][k] * X[k][j]
+                assert s == exact.Q(1 if i == j else 0)
+
+
+def test_float_oracles_vs_exact_on_tiny_integers():
+    rng = np.random.default_rng(12)
+    zs, invs, dets = [], [], []
+    while len(zs) < 400:
+        p = [int(x) for x in rng.integers(-4, 5, size=9)]
+        p[0], p[1], p[2] = (int(x) for x in rng.integers(1, 12, size=3))
+        X, det = exact.inv_det(exact.unpack(p))
+        if X is None:
+            continue
+        zs.append(p)
+        invs.append([float(v) for v in exact.pack(X)])
+        dets.append(float(det.re))
+    z = np.array(zs, dtype=np.float64).T
+    inv_ref, det_ref = np.array(invs).T, np.array(dets)
+    # integer inputs: det is an exact integer, recovered exactly in __float128
+    (ih, il), (dh, dl) = oracle.ge128(z)
+    assert np.array_equal(dh, det_ref)
+    assert np.max(oracle.inv_rel_err(ih, inv_ref)) <= 2 * U64
+    k = oracle.kappa(z)
+    inv, det = oracle.ge(z)
+    assert np.all(oracle.inv_rel_err(inv, inv_ref) <= 20 * U64 * np.maximum(k, 1))
+    assert np.all(oracle.det_rel_err(det, det_ref) <= 20 * U64 * np.maximum(k, 1))
+
+
+# --------------------------------------------------------------- mpmath 200-bit
+def test_f128_oracle_vs_mpmath():
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.prec = 200
+    rng = np.random.default_rng(13)
+    z, k = random_hpd(rng, 300, 10.0)
+    (ih, il), (dh, dl) = oracle.ge128(z)
+    (ch, cl), (cdh, cdl) = oracle.chol128(z)
+    Zf = oracle.full_from_planes(z)
+    worst_inv = worst_det = worst_chol = 0.0
+    for i in range(z.shape[1]):
+        M = mpmath.matrix([[mpmath.mpc(complex(Zf[i, r, c])) for c in range(3)] for r in range(3)])
+        Mi, Md = mpmath.inverse(M), mpmath.det(M)
+        ref = [Mi[0, 0].real, Mi[1, 1].real, Mi[2, 2].real, Mi[0, 1].real, Mi[0, 1].imag,
+               Mi[0, 2].real, Mi[0, 2].imag, Mi[1, 2].real, Mi[1, 2].imag]
+        w = [1, 1, 1, 2, 2, 2, 2, 2, 2]
+        nrm = mpmath.sqrt(sum(wk * r * r for wk, r in zip(w, ref)))
+        for hi, lo, worst in ((ih, il, "ge"), (ch, cl, "chol")):
+            e = mpmath.sqrt(sum(wk * (mpmath.mpf(hi[j, i]) + mpmath.mpf(lo[j, i]) - ref[j]) ** 2
+                                for j, wk in enumerate(w))) / nrm
+            if worst == "ge":
+                worst_inv = max(worst_inv, float(e) / k[i])
+            else:
+                worst_chol = max(worst_chol, float(e) / k[i])
+        de = abs(mpmath.mpf(dh[i]) + mpmath.mpf(dl[i]) - Md.real) / abs(Md.real)
+        worst_det = max(worst_det, float(de) / k[i])
+    u128 = 2.0 ** -113
+    assert worst_inv <= 50 * u128
+    assert worst_chol <= 50 * u128
+    assert worst_det <= 50 * u128
+
+
+# --------------------------------------------------------------- LAPACK
+def test_f64_oracles_vs_lapack():
+    rng = np.random.default_rng(14)
+    z, k = random_hpd(rng, 2000, 3.0)
+    Zf = oracle.full_from_planes(z)
+    inv_np = synth.pack(np.linalg.inv(Zf))
+    det_np = np.linalg.det(Zf).real
+    for inv, det in (oracle.ge(z), oracle.chol(z)):
+        assert np.max(oracle.inv_rel_err(inv, inv_np) / k) <= 20 * U64
+        assert np.max(oracle.det_rel_err(det, det_np) / k) <= 20 * U64
+
+
+# --------------------------------------------------------------- invariants
+def test_identity_diagonal_and_scaling():
+    z = np.zeros((9, 4))
+    z[0:3, 0] = 1.0
+    z[0:3, 1] = [4.0, 0.25, 16.0]   # powers of four: Cholesky's square roots are exact too
+    z[0:3, 2] = [4.0, 4.0, 0.0625]
+    z[0:3, 3] = [1.0, 64.0, 2.0 ** -20]
+    for inv, det in (oracle.ge(z), oracle.chol(z)):
+        assert np.array_equal(inv[0:3], 1.0 / z[0:3]) and np.all(inv[3:] == 0)
+        assert np.array_equal(det, z[0] * z[1] * z[2])
+    rng = np.random.default_rng(15)
+    zr, _ = random_hpd(rng, 50, 4.0)
+    (ih, _), (dh, _) = oracle.ge128(zr)
+    (ih2, _), (dh2, _) = oracle.ge128(zr * 2.0 ** 5)
+    assert np.array_equal(ih2, ih * 2.0 ** -5) and np.array_equal(dh2, dh * 2.0 ** 15)
+
+
+def test_residual_symmetry_and_two_forms_agree():
+    rng = np.random.default_rng(16)
+    z, k = random_hpd(rng, 5000, 8.0)
+    inv, det, chk = oracle.ge(z, checks=True)
+    Zf, Xf = oracle.full_from_planes(z), oracle.full_from_planes(inv)
+    # The packed result is made Hermitian from its upper triangle, so its
+    # residual is bounded by ||Z|| times its forward error, u*kappa^2.
+    res = np.linalg.norm(Zf @ Xf - np.eye(3), axis=(1, 2))
+    assert np.all(res <= 30 * U64 * k * k)
+    assert np.all(chk[0] <= 30 * U64 * k) and np.all(chk[1] <= 30 * U64 * k)
+    inv_c, det_c = oracle.chol(z)
+    assert np.all(oracle.inv_rel_err(inv_c, inv) <= 60 * U64 * k)
+    assert np.all(oracle.det_rel_err(det_c, det) <= 60 * U64 * k)
+    # the __float128 forms agree far below FP64 rounding
+    (ih, il), (dh, dl) = oracle.ge128(z)
+    (ch, cl), (cdh, cdl) = oracle.chol128(z)
+    w = np.array([1, 1, 1, 2, 2, 2, 2, 2, 2], dtype=np.float64)[:, None]
+    diff = (ch - ih) + (cl - il)
+    rel = np.sqrt((w * diff * diff).sum(axis=0) / (w * ih * ih).sum(axis=0))
+    assert np.all(rel <= 1e-28 * k)
+    assert np.all(np.abs((cdh - dh) + (cdl - dl)) <= 1e-28 * k * np.abs(dh))
+
+
+def _alg1_as_printed(z):
+    """Alg. 1 with l21 exactly as printed (its conjugate): a planted mistake."""
+    a, d, f, br, bi, cr, ci, er, ei = z
+    b, c, e = br + 1j * bi, cr + 1j * ci, er + 1j * ei
+    l00 = np.sqrt(a); v0 = 1 / l00
+    l10 = np.conj(b) * v0; l20 = np.conj(c) * v0
+    l11 = np.sqrt(d - abs(l10) ** 2); v1 = 1 / l11
+    l21 = (e - l10 * np.conj(l20)) * v1
+    l22 = np.sqrt(f - abs(l20) ** 2 - abs(l21) ** 2); v2 = 1 / l22
+    t10 = -l10 * v0 * v1; t20 = v2 * v0 * (l21 * l10 * v1 - l20); t21 = -l21 * v1 * v2
+    bi_ = np.conj(t10) * v1 + np.conj(t20) * t21
+    ci_ = np.conj(t20) * v2
+    ei_ = np.conj(t21) * v2
+    inv = np.stack([v0 ** 2 + abs(t10) ** 2 + abs(t20) ** 2, v1 ** 2 + abs(t21) ** 2, v2 ** 2,
+                    bi_.real, bi_.imag, ci_.real, ci_.imag, ei_.real, ei_.imag])
+    return inv, (l00 * l11 * l22) ** 2
+
+
+def test_printed_l21_is_caught_by_the_residual_pin():
+    """The pins catch a conjugation slip: with l21 as printed the determinant
+    still matches but Z X = I fails; the oracle's corrected form passes."""
+    rng = np.random.default_rng(17)
+    z, k = random_hpd(rng, 200, 2.0)
+    Zf = oracle.full_from_planes(z)
+    inv_p, det_p = _alg1_as_printed(z)
+    inv_c, det_c = oracle.chol(z)
+    assert np.allclose(det_p, det_c, rtol=1e-12)
+    res_p = np.linalg.norm(Zf @ oracle.full_from_planes(inv_p) - np.eye(3), axis=(1, 2))
+    res_c = np.linalg.norm(Zf @ oracle.full_from_planes(inv_c) - np.eye(3), axis=(1, 2))
+    assert np.median(res_p) > 1e-2
+    assert np.all(res_c <= 30 * U64 * k * k)
+
+
+def test_pd_class():
+    z = np.zeros((9, 5))
+    z[0:3, 0] = 1.0                                    # identity
+    z[0:3, 1] = [1.0, 1.0, 1.0]; z[3, 1] = 1.0          # [[1,1,0],[1,1,0],[0,0,1]]: singular
+    z[0:3, 2] = [1.0, -1.0, 1.0]                        # indefinite
+    z[0:3, 3] = [1.0, 1.0, 1.0]; z[4, 3] = np.nan       # non-finite
+    z[0:3, 4] = [0.0, 1.0, 1.0]                         # zero pivot
+    assert list(oracle.pd_class(z)) == [0, 2, 2, 3, 2]
+    rng = np.random.default_rng(18)
+    zr, _ = random_hpd(rng, 1000, 6.0)
+    assert np.all(oracle.pd_class(zr) == 0)
+
+
+# --------------------------------------------------------------- Wishart
+def test_wishart_closed_forms():
+    rng = np.random.default_rng(19)
+    z, _ = random_hpd(rng, 500, 2.0)
+    N = 8.0
+    ell, g = oracle.wishart(z, z, N)
+    (eh, el), (gh, gl) = oracle.wishart128(z, z, N)
+    det_z = np.linalg.det(oracle.full_from_planes(z)).real
+    assert np.allclose(ell, N * (np.log(det_z) + 3.0), rtol=1e-12, atol=1e-12)
+    assert np.allclose(eh, N * (np.log(det_z) + 3.0), rtol=1e-13, atol=1e-13)
+    gscale = N * np.abs(oracle.ge(z)[0]).max(axis=0)
+    assert np.all(np.abs(g).max(axis=0) <= 1e-10 * gscale)
+    assert np.all(np.abs(gh).max(axis=0) <= 1e-25 * gscale)
+    # S = alpha Z, with the worked example's exact inverse
+    gld = json.load(open(GOLDEN))
+    zw = np.array(gld["z"], dtype=np.float64)[:, None]
+    zinv = np.array([float(F(s)) for s in gld["inverse"]])[:, None]
+    for alpha in (0.5, 2.0, 3.0):
+        (eh, el), (gh, gl) = oracle.wishart128(alpha * zw, zw, N)
+        want = N * (math.log(80.0) + 3 * math.log(alpha) + 3 / alpha)
+        assert abs(eh[0] - want) <= 1e-14 * abs(want)
+        w = np.array([1, 1, 1, 2, 2, 2, 2, 2, 2], dtype=np.float64)[:, None]
+        want_g = N * (1 / alpha - 1 / alpha ** 2) * w * zinv
+        assert np.allclose(gh, want_g, rtol=1e-15, atol=1e-16)
+
+
+def test_wishart_gradient_vs_finite_differences():
+    """Central differences of the __float128 per-pixel term, one packed real
+    parameter at a time (step 1e-6 times the mean eigenvalue)."""
+    rng = np.random.default_rng(20)
+    img = synth.make_image(16, 16, 8, (2, 2), (1e-2, 1.0), 3)
+    z = img.planes.reshape(9, -1)
+    s = synth.wishart_sigma0(z)
+    N = 8.0
+    (_, _), (gh, gl) = oracle.wishart128(s, z, N)
+    h = 1e-6 * (s[0] + s[1] + s[2]) / 3.0
+    fd = np.empty_like(gh)
+    for k in range(9):
+        sp, sm = s.copy(), s.copy()
+        sp[k] += h
+        sm[k] -= h
+        (ep, epl), _ = oracle.wishart128(sp, z, N, grad=False)
+        (em, eml), _ = oracle.wishart128(sm, z, N, grad=False)
+        hk = sp[k] - sm[k]  # the step actually taken, exactly representable
+        fd[k] = ((ep - em) + (epl - eml)) / hk
+    err = np.linalg.norm(fd - gh, axis=0) / np.linalg.norm(gh, axis=0)
+    assert np.max(err) <= 1e-5
+    # FP64 oracle gradient against the __float128 one
+    _, g64 = oracle.wishart(s, z, N)
+    assert np.max(np.linalg.norm(g64 - gh, axis=0) / np.linalg.norm(gh, axis=0)) <= 1e-12
