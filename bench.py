@@ -1,0 +1,195 @@
+"""Throughput of the per-pixel 3x3 Hermitian inverse + determinant on one MI355X.
+
+Workload: a 4096x4096 synthetic PolSAR image, N=4 looks, 4x4 regions, region
+eigenvalues log-uniform in [1e-3, 1], seed 1; FP32 planes (36 B in, 40 B out
+per pixel).  One step = one polsar_inv_det call over the whole image with the
+adjugate method, compensated FP32 arithmetic and FP64 recompute of flagged
+pixels, data resident in HBM.  Beside it the same image is timed with the
+Cholesky form and other precisions, the Wishart forward+backward and a plane
+copy of the same byte count (measured bandwidth ceiling); the CPU oracle is
+timed on the host.  Prints one JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-rows]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+PEAK_HBM_GBS = 8000.0
+WORKLOAD = {"workload": "polsar-4096x4096-N4-16regions-lam1e-3", "height": 4096, "width": 4096,
+            "n_looks": 4, "regions": "4x4", "lam_range": [1e-3, 1.0], "seed": 1,
+            "method": "adjugate", "precision": "fp32-compensated+fp64-reroute", "planes": "SoA 9 in, 9+1 out"}
+BYTES_PER_PX = {"f32": 76, "f64": 152}         # 9 planes in + 9 inverse planes + det
+WISHART_BYTES_PER_PX = {"f32": 108, "f64": 216}  # fused fwd+bwd: S, Z in (72) + grad out (36)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "paper_1807_08084_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel: str, n_px: int):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(HERE, "profiles", "hbm_traffic_inv_det_4096.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            rec[k.strip()] = v.strip()
+    if rec.get("source_hash") != kernel_source_hash() or rec.get("kernel") != kernel:
+        return None
+    try:
+        return float(rec["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_calls(fn, steps: int, warmup: int, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps  # ms per call
+
+
+def cpu_baseline(z64: np.ndarray, n_px: int, min_seconds: float = 10.0):
+    import oracle
+    threads = oracle.threads()
+    oracle.ge(z64[:, :1024], nthreads=threads)  # load + warm
+    t0 = time.perf_counter()
+    passes = 0
+    while True:
+        oracle.ge(z64, nthreads=threads)
+        passes += 1
+        el = time.perf_counter() - t0
+        if el >= min_seconds or passes >= 50:
+            break
+    return {"value": passes * n_px / el / 1e9, "unit": "Gpixel/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 Gaussian-elimination oracle (OpenMP, {threads} threads) over the whole "
+                      f"{n_px}-pixel image, {passes} passes, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-rows", action="store_true")
+    ap.add_argument("--tune", action="store_true", help="autotune the launch before timing")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(every pixel is independent: see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1807_08084_amd import synth
+    t = time.perf_counter()
+    img = synth.workload_scale()
+    z64 = img.planes.reshape(9, -1)
+    n_px = z64.shape[1]
+    print(f"# generated {n_px} px in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+
+    import torch
+    from paper_1807_08084_amd import ops
+    dev = torch.device("cuda:0")
+    z32 = torch.from_numpy(z64.astype(np.float32)).to(dev)
+    inv = torch.empty_like(z32)
+    det = torch.empty(n_px, dtype=torch.float32, device=dev)
+    if args.tune:
+        cfg, ms = ops.autotune_inv_det(z32, "adjugate", "compensated", reps=5)
+        print(f"# tuned {cfg} {ms:.3f} ms", file=sys.stderr, flush=True)
+
+    def step():
+        ops.inv_det(z32, "adjugate", "compensated", inv=inv, det=det)
+
+    ms = time_calls(step, args.steps, args.warmup, torch)
+    value = n_px / (ms * 1e-3) / 1e9
+    achieved = BYTES_PER_PX["f32"] * n_px / (ms * 1e-3) / 1e9
+    kname = "k_inv_det<float, ADJ_COMP>"
+    traffic = traffic_from_profiles(kname, n_px)
+    out = {
+        "metric": "Gpixel/s inv+det & %HBM roofline, adjugate vs Cholesky, 1 MI355X",
+        "value": round(value, 3), "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": WORKLOAD,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "kernel": kname, "algorithmic_bytes_per_px": BYTES_PER_PX["f32"],
+                     "launch": ops.get_launch(0, torch.float32, "adjugate", "compensated")},
+    }
+
+    if not args.no_rows:
+        rows = {}
+        ksteps = max(10, args.steps // 2)
+        for dt, tname in ((torch.float32, "f32"), (torch.float64, "f64")):
+            zt = z32 if dt == torch.float32 else torch.from_numpy(z64).to(dev)
+            it = torch.empty_like(zt)
+            de = torch.empty(n_px, dtype=dt, device=dev)
+            combos = [("adjugate", "compensated"), ("adjugate", "plain"), ("cholesky", "plain")]
+            if dt == torch.float32:
+                combos += [("adjugate", "wide"), ("cholesky", "compensated"), ("cholesky", "wide")]
+            for m, p in combos:
+                f = (lambda m=m, p=p: ops.inv_det(zt, m, p, inv=it, det=de))
+                t_ms = time_calls(f, ksteps, 3, torch)
+                gbs = BYTES_PER_PX[tname] * n_px / (t_ms * 1e-3) / 1e9
+                rows[f"{m}_{p}_{tname}"] = {"gpx_s": round(n_px / t_ms / 1e6, 3), "ms": round(t_ms, 4),
+                                           "GB_s": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)}
+            dst = torch.empty((10, n_px), dtype=dt, device=dev)
+            c_ms = time_calls(lambda: ops.stream_copy(zt, dst, 9, 10, n_px), ksteps, 3, torch)
+            cgbs = BYTES_PER_PX[tname] * n_px / (c_ms * 1e-3) / 1e9
+            rows[f"copy_9to10_{tname}"] = {"ms": round(c_ms, 4), "GB_s": round(cgbs, 1),
+                                          "frac_hbm": round(cgbs / PEAK_HBM_GBS, 4)}
+            del it, de, dst
+            # Wishart forward+backward (fused): S = Z + 0.1 tr(Z)/3 I against Z
+            sig = zt.clone()
+            tr = (zt[0] + zt[1] + zt[2]) * (0.1 / 3.0)
+            for k in range(3):
+                sig[k] += tr
+            ws = torch.empty(max(1, ops.workspace_bytes(dt, n_px) // 8 + 1), dtype=torch.float64, device=dev)
+            w_ms = time_calls(lambda: ops.wishart_loglik(sig, zt, 4.0, forward=True, backward=True,
+                                                         workspace=ws), ksteps, 3, torch)
+            wgbs = WISHART_BYTES_PER_PX[tname] * n_px / (w_ms * 1e-3) / 1e9
+            rows[f"wishart_fwd_bwd_{tname}"] = {"gpx_s": round(n_px / w_ms / 1e6, 3), "ms": round(w_ms, 4),
+                                               "GB_s": round(wgbs, 1), "frac_hbm": round(wgbs / PEAK_HBM_GBS, 4)}
+            del sig, ws
+        adj = rows["adjugate_compensated_f32"]["ms"]
+        out["rows"] = rows
+        out["copy_ceiling_frac"] = round(rows["copy_9to10_f32"]["ms"] / ms, 4)
+        out["speedup_adjugate_vs_cholesky"] = {
+            "f32_plain": round(rows["cholesky_plain_f32"]["ms"] / rows["adjugate_plain_f32"]["ms"], 3),
+            "f32_equal_accuracy_vs_cholesky_fallback": round(rows["cholesky_compensated_f32"]["ms"] / adj, 3),
+            "f32_equal_accuracy_vs_cholesky_wide": round(rows["cholesky_wide_f32"]["ms"] / adj, 3),
+            "f64_plain": round(rows["cholesky_plain_f64"]["ms"] / rows["adjugate_plain_f64"]["ms"], 3),
+            "paper_context": "about 2.2x on a GeForce 940M, OpenCL (Table 2)"}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(z64.astype(np.float32).astype(np.float64), n_px)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/* polsar.h -- per-pixel inverse and determinant of 3x3 complex Hermitian
+ * positive-definite matrices (PolSAR multilook covariances), and the Wishart
+ * log-likelihood with its gradient, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Coelho, Cintra, Frery, Dimitrov, "Fast Matrix Inversion and
+ * Determinant Computation for Polarimetric Synthetic Aperture Radar":
+ * Alg. 2 (adjugate + real-part determinant, Section 3.1) is the method;
+ * Alg. 1 (Cholesky, Section 2.2) is built beside it for comparison.
+ *
+ * DATA LAYOUT.  A batch of n matrices is nine planes of n reals each
+ * (structure of arrays).  Plane k starts at base + k*pitch elements:
+ *     k = 0:a  1:d  2:f  3:Re b  4:Im b  5:Re c  6:Im c  7:Re e  8:Im e
+ * for A = [[a, b, c], [conj(b), d, e], [conj(c), conj(e), f]] (the upper
+ * triangle, Section 2.1).  Inverses and gradients use the same packing.
+ * Element type is float (POLSAR_F32) or double (POLSAR_F64) for every plane
+ * of one call.  pitch >= n.  Pointers must be aligned to the element size;
+ * when every plane base is 16-byte aligned (base and pitch*element size
+ * multiples of 16, and the status plane 4-byte aligned for F32, 2-byte for
+ * F64) the kernels move 128 bits per access, otherwise one element.
+ *
+ * MEMORY AND STREAMS.  Unless stated, pointers are DEVICE pointers on the
+ * current HIP device; the caller allocates and owns every buffer, the library
+ * never frees caller memory.  Every call is asynchronous on `stream` (a
+ * hipStream_t; NULL = the default stream); buffers must stay valid until the
+ * stream reaches the work.
+ *
+ * ERRORS.  Calls return POLSAR_OK or a negative polsar_status.  Argument
+ * errors are detected before any HIP call.  Per-pixel numerical outcomes are
+ * never call errors: they go to the optional status plane (one byte per
+ * pixel, POLSAR_PX_*) and to the optional counters (device array of three
+ * unsigned 64-bit integers [not_pd, rerouted, nonfinite], ADDED to, so the
+ * caller zeroes them).  n == 0 is a no-op returning POLSAR_OK (plane
+ * pointers and the workspace may then be NULL; a forward Wishart pass still
+ * writes a loss of 0).
+ * Reentrant: calls share no mutable state except the launch-configuration
+ * table, which is guarded.
+ */
+#ifndef POLSAR_H
+#define POLSAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  POLSAR_OK = 0,
+  POLSAR_E_ARG = -1,         /* null/negative/out-of-range argument, pitch < n */
+  POLSAR_E_ALIGN = -2,       /* pointer not aligned to its element size */
+  POLSAR_E_UNSUPPORTED = -3, /* valid enums, combination not provided */
+  POLSAR_E_HIP = -4,         /* a HIP runtime call or launch failed */
+  POLSAR_E_WORKSPACE = -5,   /* workspace missing or too small */
+  POLSAR_E_ALIAS = -6        /* outputs overlap inputs (other than exact in-place) */
+} polsar_status;
+
+typedef enum { POLSAR_F32 = 0, POLSAR_F64 = 1 } polsar_dtype;
+typedef enum { POLSAR_ADJUGATE = 0, POLSAR_CHOLESKY = 1 } polsar_method;
+
+/* Arithmetic of one call.
+ *   PLAIN        the algorithm in the storage type.
+ *   COMPENSATED  ADJUGATE: Dot2-compensated cofactors and determinant (FMA
+ *                error-free products and sums); in F32, pixels whose
+ *                a-posteriori determinant error bound exceeds 1e-6 relative,
+ *                or whose det is not positive or not finite, are recomputed
+ *                by the compensated F64 path (status POLSAR_PX_REROUTED).
+ *                CHOLESKY (F32 only): F32, pixels whose pivots fail
+ *                recomputed in F64.
+ *   WIDE         F32 storage, F64 arithmetic (F32 only). */
+typedef enum { POLSAR_PLAIN = 0, POLSAR_COMPENSATED = 1, POLSAR_WIDE = 2 } polsar_precision;
+
+/* Per-pixel status values. */
+enum { POLSAR_PX_OK = 0, POLSAR_PX_REROUTED = 1, POLSAR_PX_NOT_PD = 2, POLSAR_PX_NONFINITE = 3 };
+
+/* Inverse and determinant of n packed Hermitian matrices (Alg. 2, Section
+ * 3.1: cofactors of Eq. adjoint_elements, determinant of Eq. detr, t = 1/det,
+ * inverse = t * adjugate per Eq. inv_adjoint; or Alg. 1 for CHOLESKY).
+ *   z       in: 9 planes, pitch z_pitch
+ *   inv     out (nullable): 9 planes of the inverse's upper triangle; may be
+ *           exactly z with inv_pitch == z_pitch (in place)
+ *   det     out (nullable): n determinants
+ *   status  out (nullable): n bytes, POLSAR_PX_*
+ *   counters in/out (nullable): 3 x uint64 added to
+ * Outputs for non-positive-definite or singular pixels are the IEEE results
+ * of the formulas (possibly Inf/NaN) with the status set. */
+int polsar_inv_det(int dtype, int method, int precision, int64_t n,
+                   const void* z, int64_t z_pitch,
+                   void* inv, int64_t inv_pitch, void* det,
+                   uint8_t* status, unsigned long long* counters, void* stream);
+
+typedef enum { POLSAR_FWD = 1, POLSAR_BWD = 2, POLSAR_FWD_BWD = 3 } polsar_pass;
+
+/* Wishart log-likelihood term, summed over pixels:
+ *   L = sum_px N (ln det S + tr(S^-1 Z))
+ * (the densities of the Introduction depend on the covariance only through
+ * its determinant and inverse; the Sigma-free terms of the complex Wishart
+ * density are omitted), with S^-1 and det S from Alg. 2 in the storage type,
+ * and its gradient with respect to the packed real parameters of S:
+ *   grad = g N (P - P Z P), P = S^-1 recomputed, off-diagonal components
+ *   doubled: (M00, M11, M22, 2Re M01, 2Im M01, 2Re M02, 2Im M02, 2Re M12, 2Im M12).
+ *   sigma, z   in: 9 planes each (pitches s_pitch, z_pitch)
+ *   n_looks    N (> 0)
+ *   loss       out (FWD, FWD_BWD): one device double, overwritten with L
+ *   ell        out (nullable): n per-pixel terms, storage type
+ *   grad_loss  in (BWD, FWD_BWD; nullable = 1.0): device double g
+ *   grad       out (BWD, FWD_BWD): 9 planes, pitch g_pitch
+ *   workspace  device scratch of at least polsar_wishart_workspace_bytes(n)
+ *              bytes (FWD, FWD_BWD), 8-byte aligned; holds per-tile FP64
+ *              partial sums, reduced in a fixed order (deterministic).
+ *   counters   as for polsar_inv_det ([not_pd, 0, nonfinite] for S). */
+int polsar_wishart_loglik(int dtype, int pass, int64_t n,
+                          const void* sigma, int64_t s_pitch,
+                          const void* z, int64_t z_pitch, double n_looks,
+                          double* loss, void* ell, const double* grad_loss,
+                          void* grad, int64_t g_pitch,
+                          void* workspace, size_t ws_bytes,
+                          unsigned long long* counters, void* stream);
+size_t polsar_wishart_workspace_bytes(int dtype, int64_t n);
+
+/* Batched persistent launch over many images of uneven sizes (one grid walks
+ * the tiles of all images; the launch and the per-image loss reduction are
+ * captured once in a HIP graph).  Per image, any of: inverse/determinant of
+ * Z (ops & POLSAR_OP_INV_DET), Wishart forward (loss, ell) and backward
+ * (grad) of S against Z (ops & POLSAR_OP_WISHART_FWD / _BWD).  Host array
+ * `imgs`; the pointers inside are device pointers with the meaning above,
+ * `loss` one device double per image.  grad_loss (device double, nullable =
+ * 1.0) scales every gradient. */
+enum { POLSAR_OP_INV_DET = 1, POLSAR_OP_WISHART_FWD = 2, POLSAR_OP_WISHART_BWD = 4 };
+typedef struct {
+  int64_t n;
+  const void* z;     int64_t z_pitch;
+  void* inv;         int64_t inv_pitch;
+  void* det;
+  uint8_t* status;
+  const void* sigma; int64_t s_pitch;
+  void* grad;        int64_t g_pitch;
+  void* ell;
+  double* loss;
+  double n_looks;
+} polsar_image;
+typedef struct polsar_batch polsar_batch;
+
+/* Allocates device tables, a workspace and the graph (the only call that
+ * allocates).  method: POLSAR_ADJUGATE or POLSAR_CHOLESKY for the inverse;
+ * grid_per_cu 0 = tuned default.  Returns POLSAR_OK and *out, or an error
+ * (no allocation left behind). */
+int polsar_batch_create(const polsar_image* imgs, int count, int dtype, int method,
+                        int precision, unsigned ops, const double* grad_loss,
+                        unsigned long long* counters, int grid_per_cu,
+                        polsar_batch** out);
+int polsar_batch_run(polsar_batch* b, void* stream);        /* one hipGraphLaunch */
+int polsar_batch_run_eager(polsar_batch* b, void* stream);  /* same kernels, no graph */
+int64_t polsar_batch_tiles(const polsar_batch* b);
+void polsar_batch_destroy(polsar_batch* b);
+
+/* Launch configuration of the per-call kernels (inverse/determinant and
+ * Wishart), keyed by op (0 = inv_det, 1 = wishart), dtype, method, precision.
+ *   block        threads per block: 64, 128 or 256
+ *   unroll       128-bit vectors per thread per tile: 1, 2 or 4
+ *   grid_per_cu  0 = one tile per block; k > 0 = persistent grid of k blocks
+ *                per compute unit striding over tiles
+ *   nontemporal  1 = streaming (non-temporal) loads and stores */
+typedef struct { int block, unroll, grid_per_cu, nontemporal; } polsar_launch;
+int polsar_get_launch(int op, int dtype, int method, int precision, polsar_launch* out);
+int polsar_set_launch(int op, int dtype, int method, int precision, const polsar_launch* cfg);
+
+/* Times each candidate launch configuration of polsar_inv_det on the caller's
+ * buffers (same arguments as polsar_inv_det; outputs are overwritten), `reps`
+ * timed repetitions each after one warm-up, installs the fastest and returns
+ * it with its mean time in milliseconds.  Synchronises `stream`. */
+int polsar_autotune_inv_det(int dtype, int method, int precision, int64_t n,
+                            const void* z, int64_t z_pitch, void* inv, int64_t inv_pitch,
+                            void* det, int reps, polsar_launch* best, float* best_ms,
+                            void* stream);
+
+/* Bandwidth probe: copies n_in planes of n elements (pitch src_pitch) to
+ * n_out planes (pitch dst_pitch; plane k of dst takes plane k mod n_in) with
+ * the same access pattern as the inverse kernels, for a measured ceiling. */
+int polsar_stream_copy(int dtype, int64_t n, const void* src, int64_t src_pitch, int n_in,
+                       void* dst, int64_t dst_pitch, int n_out, void* stream);
+
+const char* polsar_status_string(int status);
+const char* polsar_version(void);
+int polsar_device_compute_units(int* cus);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POLSAR_H */

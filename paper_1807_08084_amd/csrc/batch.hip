@@ -1,0 +1,379 @@
+// Batched persistent launch over many images of uneven sizes.
+//
+// The images' pixels are cut into tiles of `block` vectors (one vector per
+// lane, V pixels per vector on the 128-bit path), numbered consecutively
+// image after image.  One persistent grid (k blocks per compute unit)
+// strides over the global tile numbers; a block finds its image by binary
+// search over the images' first tiles.  Per tile it loads Z once and, as the
+// batch asks, writes the inverse/determinant of Z, and the Wishart term and
+// gradient of S against the same Z.  Wishart partial sums are kept per tile
+// and reduced per image in a fixed order by a second kernel, so the losses
+// do not depend on the grid.  Both launches are captured in one HIP graph at
+// creation; running the batch is one graph launch.
+//
+// The tile cut and the per-pixel functions are those of the per-call
+// kernels at unroll 1, so every per-pixel output is bitwise equal to a
+// per-image call with the same block size.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/polsar.h"
+#include "common.hpp"
+
+namespace {
+using namespace polsar_dev;
+
+struct ImgDesc {
+  const void* z;
+  void* inv;
+  void* det;
+  uint8_t* status;
+  const void* sigma;
+  void* grad;
+  void* ell;
+  double* loss;
+  int64_t n, zp, ip, sp, gp;
+  double n_looks;
+  int64_t tile0;   // first global tile of this image
+  int64_t ntiles;  // tiles of this image
+  int64_t nvec;    // full vectors on this image's path
+  int vec;         // 1: 128-bit path, 0: one element per access
+  int pad;
+};
+
+struct BatchArgs {
+  const ImgDesc* img;
+  int count;
+  int64_t total_tiles;
+  double* partial;  // one per global tile
+  const double* grad_loss;
+  unsigned long long* counters;
+  int do_inv, do_fwd, do_bwd;
+};
+
+// This lane's vector of local tile lt of image d (the cut of the per-call
+// kernels at unroll 1), plus the image's tail pixels in its last tile.
+// Returns the lane's sum of Wishart terms.
+template <class T, int OP, int V, bool NT>
+__device__ __forceinline__ double batch_tile(const BatchArgs& a, const ImgDesc& d, int64_t lt, T gscale,
+                                             unsigned& c0, unsigned& c1, unsigned& c2) {
+  const T* __restrict__ Z = (const T*)d.z;
+  const T* __restrict__ S = (const T*)d.sigma;
+  const int64_t v = lt * (int64_t)blockDim.x + threadIdx.x;
+  const bool wish = a.do_fwd || a.do_bwd;
+  double acc = 0.0;
+  if (v < d.nvec) {
+    T z[9][V], s[9][V];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) load_v<T, V, NT>(Z + k * d.zp + v * V, z[k]);
+    if (wish)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) load_v<T, V, NT>(S + k * d.sp + v * V, s[k]);
+    const int64_t e = v * V;
+    if (a.do_inv) {
+      T out[9][V], dt[V];
+      int st[V];
+#pragma unroll
+      for (int l = 0; l < V; ++l) {
+        T zz[9], xx[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) zz[k] = z[k][l];
+        st[l] = run_pixel<T, OP>(zz, xx, dt[l]);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) out[k][l] = xx[k];
+        tally(st[l], c0, c1, c2);
+      }
+      if (d.inv)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) store_v<T, V, NT>((T*)d.inv + k * d.ip + e, out[k]);
+      if (d.det) store_v<T, V, NT>((T*)d.det + e, dt);
+      if (d.status) store_status<V>(d.status + e, st);
+    }
+    if (wish) {
+      T ell[V], g[9][V];
+#pragma unroll
+      for (int l = 0; l < V; ++l) {
+        T ss[9], zz[9], gg[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) { ss[k] = s[k][l]; zz[k] = z[k][l]; }
+        px::wishart_pixel<T>(ss, zz, (T)d.n_looks, a.do_fwd ? &ell[l] : nullptr, a.do_bwd ? gg : nullptr, gscale);
+        if (a.do_fwd) acc += (double)ell[l];
+        if (a.do_bwd)
+#pragma unroll
+          for (int k = 0; k < 9; ++k) g[k][l] = gg[k];
+      }
+      if (a.do_fwd && d.ell) store_v<T, V, NT>((T*)d.ell + e, ell);
+      if (a.do_bwd)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) store_v<T, V, NT>((T*)d.grad + k * d.gp + e, g[k]);
+    }
+  }
+  if (V > 1 && lt == d.ntiles - 1) {
+    const int64_t i = d.nvec * V + threadIdx.x;
+    if (i < d.n) {
+      T zz[9], ss[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) zz[k] = Z[k * d.zp + i];
+      if (a.do_inv) {
+        T xx[9], dt;
+        const int st = run_pixel<T, OP>(zz, xx, dt);
+        tally(st, c0, c1, c2);
+        if (d.inv)
+#pragma unroll
+          for (int k = 0; k < 9; ++k) ((T*)d.inv)[k * d.ip + i] = xx[k];
+        if (d.det) ((T*)d.det)[i] = dt;
+        if (d.status) d.status[i] = (uint8_t)st;
+      }
+      if (wish) {
+        T gg[9], el;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) ss[k] = S[k * d.sp + i];
+        px::wishart_pixel<T>(ss, zz, (T)d.n_looks, a.do_fwd ? &el : nullptr, a.do_bwd ? gg : nullptr, gscale);
+        if (a.do_fwd) {
+          acc += (double)el;
+          if (d.ell) ((T*)d.ell)[i] = el;
+        }
+        if (a.do_bwd)
+#pragma unroll
+          for (int k = 0; k < 9; ++k) ((T*)d.grad)[k * d.gp + i] = gg[k];
+      }
+    }
+  }
+  return acc;
+}
+
+template <class T, int OP, bool NT>
+__global__ __launch_bounds__(256) void k_batch(BatchArgs a) {
+  constexpr int VW = 16 / sizeof(T);
+  const T gscale = a.do_bwd ? (a.grad_loss ? (T)*a.grad_loss : T(1)) : T(1);
+  unsigned c0 = 0, c1 = 0, c2 = 0;
+  for (int64_t t = blockIdx.x; t < a.total_tiles; t += gridDim.x) {
+    // image owning global tile t: last i with img[i].tile0 <= t
+    int lo = 0, hi = a.count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.img[mid].tile0 <= t) lo = mid; else hi = mid - 1;
+    }
+    const ImgDesc& d = a.img[lo];
+    const int64_t lt = t - d.tile0;
+    const double acc = d.vec ? batch_tile<T, OP, VW, NT>(a, d, lt, gscale, c0, c1, c2)
+                             : batch_tile<T, OP, 1, NT>(a, d, lt, gscale, c0, c1, c2);
+    if (a.do_fwd) {
+      const double bs = block_sum(acc);
+      if (threadIdx.x == 0) a.partial[t] = bs;
+    }
+  }
+  if (a.counters) flush_counters(a.counters, c0, c1, c2);
+}
+
+// One block per image: fixed-order sum of its tiles' partials into loss.
+__global__ __launch_bounds__(256) void k_batch_reduce(const ImgDesc* __restrict__ img, const double* __restrict__ partial) {
+  const ImgDesc& d = img[blockIdx.x];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < d.ntiles; i += blockDim.x) s += partial[d.tile0 + i];
+  s = block_sum(s);
+  if (threadIdx.x == 0 && d.loss) *d.loss = s;
+}
+
+int device_cus_b() {
+  int dev = 0, cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) return 256;
+  return cu;
+}
+
+}  // namespace
+
+struct polsar_batch {
+  int dtype, op, count;
+  unsigned ops;
+  int block, grid;
+  int nt;
+  int64_t total_tiles;
+  ImgDesc* d_img;
+  double* d_partial;
+  BatchArgs args;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+namespace {
+
+hipError_t enqueue(const polsar_batch* b, hipStream_t s) {
+  const int op = b->op;
+#define POLSAR_BATCH(T, OPV)                                                                                    \
+  do {                                                                                                         \
+    if (b->nt) hipLaunchKernelGGL((k_batch<T, OPV, true>), dim3(b->grid), dim3(b->block), 0, s, b->args);      \
+    else hipLaunchKernelGGL((k_batch<T, OPV, false>), dim3(b->grid), dim3(b->block), 0, s, b->args);           \
+  } while (0)
+  if (b->dtype == POLSAR_F32) {
+    switch (op) {
+      case ADJ_PLAIN: POLSAR_BATCH(float, ADJ_PLAIN); break;
+      case ADJ_COMP: POLSAR_BATCH(float, ADJ_COMP); break;
+      case ADJ_WIDE: POLSAR_BATCH(float, ADJ_WIDE); break;
+      case CHOL_PLAIN: POLSAR_BATCH(float, CHOL_PLAIN); break;
+      case CHOL_COMP: POLSAR_BATCH(float, CHOL_COMP); break;
+      default: POLSAR_BATCH(float, CHOL_WIDE); break;
+    }
+  } else {
+    switch (op) {
+      case ADJ_PLAIN: POLSAR_BATCH(double, ADJ_PLAIN); break;
+      case ADJ_COMP: POLSAR_BATCH(double, ADJ_COMP); break;
+      default: POLSAR_BATCH(double, CHOL_PLAIN); break;
+    }
+  }
+#undef POLSAR_BATCH
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (b->ops & POLSAR_OP_WISHART_FWD) {
+    hipLaunchKernelGGL(k_batch_reduce, dim3(b->count), dim3(256), 0, s, (const ImgDesc*)b->d_img,
+                       (const double*)b->d_partial);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+void release(polsar_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->d_img) (void)hipFree(b->d_img);
+  if (b->d_partial) (void)hipFree(b->d_partial);
+  delete b;
+}
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int polsar_batch_create(const polsar_image* imgs, int count, int dtype, int method, int precision, unsigned ops,
+                        const double* grad_loss, unsigned long long* counters, int grid_per_cu,
+                        polsar_batch** out) {
+  if (!out) return POLSAR_E_ARG;
+  *out = nullptr;
+  if (!imgs || count <= 0 || count > (1 << 20)) return POLSAR_E_ARG;
+  if (dtype != POLSAR_F32 && dtype != POLSAR_F64) return POLSAR_E_ARG;
+  if (method != POLSAR_ADJUGATE && method != POLSAR_CHOLESKY) return POLSAR_E_ARG;
+  if (precision != POLSAR_PLAIN && precision != POLSAR_COMPENSATED && precision != POLSAR_WIDE) return POLSAR_E_ARG;
+  if (ops == 0 || (ops & ~7u)) return POLSAR_E_ARG;
+  if (dtype == POLSAR_F64 && precision == POLSAR_WIDE) return POLSAR_E_UNSUPPORTED;
+  if (dtype == POLSAR_F64 && method == POLSAR_CHOLESKY && precision != POLSAR_PLAIN) return POLSAR_E_UNSUPPORTED;
+  if (grid_per_cu < 0 || grid_per_cu > 64) return POLSAR_E_ARG;
+  if (grad_loss && !aligned(grad_loss, 8)) return POLSAR_E_ALIGN;
+  if (counters && !aligned(counters, 8)) return POLSAR_E_ALIGN;
+  const size_t es = dtype == POLSAR_F64 ? 8 : 4;
+  const int VW = (int)(16 / es);
+  // Tile size: that of the per-call Wishart kernel when the batch evaluates
+  // the Wishart term (so per-image losses are summed in the same order),
+  // else that of the per-call inverse kernel.
+  polsar_launch cfg, wcfg;
+  polsar_get_launch(0, dtype, method, precision, &cfg);
+  polsar_get_launch(1, dtype, 0, 0, &wcfg);
+  const int block = (ops & (POLSAR_OP_WISHART_FWD | POLSAR_OP_WISHART_BWD)) ? wcfg.block : cfg.block;
+  std::vector<ImgDesc> h(count);
+  int64_t tiles = 0;
+  for (int i = 0; i < count; ++i) {
+    const polsar_image& m = imgs[i];
+    if (m.n <= 0) return POLSAR_E_ARG;
+    auto planes_ok = [&](const void* p, int64_t pitch) {
+      return p && pitch >= m.n && aligned(p, es);
+    };
+    if (!planes_ok(m.z, m.z_pitch)) return POLSAR_E_ARG;
+    bool vec = aligned(m.z, 16) && (m.z_pitch * (int64_t)es) % 16 == 0;
+    if (ops & POLSAR_OP_INV_DET) {
+      if (!m.inv && !m.det && !m.status) return POLSAR_E_ARG;
+      if (m.inv && !planes_ok(m.inv, m.inv_pitch)) return POLSAR_E_ARG;
+      if (m.det && !aligned(m.det, es)) return POLSAR_E_ALIGN;
+      if (m.inv) vec = vec && aligned(m.inv, 16) && (m.inv_pitch * (int64_t)es) % 16 == 0;
+      if (m.det) vec = vec && aligned(m.det, 16);
+      if (m.status) vec = vec && aligned(m.status, VW);
+    }
+    if (ops & (POLSAR_OP_WISHART_FWD | POLSAR_OP_WISHART_BWD)) {
+      if (!planes_ok(m.sigma, m.s_pitch) || !(m.n_looks > 0.0)) return POLSAR_E_ARG;
+      vec = vec && aligned(m.sigma, 16) && (m.s_pitch * (int64_t)es) % 16 == 0;
+    }
+    if (ops & POLSAR_OP_WISHART_FWD) {
+      if (!m.loss || !aligned(m.loss, 8)) return POLSAR_E_ARG;
+      if (m.ell) vec = vec && aligned(m.ell, 16);
+    }
+    if (ops & POLSAR_OP_WISHART_BWD) {
+      if (!planes_ok(m.grad, m.g_pitch)) return POLSAR_E_ARG;
+      vec = vec && aligned(m.grad, 16) && (m.g_pitch * (int64_t)es) % 16 == 0;
+    }
+    ImgDesc& d = h[i];
+    d.z = m.z;
+    d.inv = (ops & POLSAR_OP_INV_DET) ? m.inv : nullptr;
+    d.det = (ops & POLSAR_OP_INV_DET) ? m.det : nullptr;
+    d.status = (ops & POLSAR_OP_INV_DET) ? m.status : nullptr;
+    d.sigma = m.sigma;
+    d.grad = m.grad;
+    d.ell = (ops & POLSAR_OP_WISHART_FWD) ? m.ell : nullptr;
+    d.loss = m.loss;
+    d.n = m.n;
+    d.zp = m.z_pitch;
+    d.ip = m.inv_pitch;
+    d.sp = m.s_pitch;
+    d.gp = m.g_pitch;
+    d.n_looks = m.n_looks;
+    d.vec = vec ? 1 : 0;
+    d.pad = 0;
+    d.nvec = m.n / (vec ? VW : 1);
+    d.ntiles = std::max<int64_t>(1, (d.nvec + block - 1) / block);
+    d.tile0 = tiles;
+    tiles += d.ntiles;
+  }
+  polsar_batch* b = new polsar_batch();
+  b->dtype = dtype;
+  b->count = count;
+  b->ops = ops;
+  b->op = method == POLSAR_ADJUGATE ? (precision == POLSAR_PLAIN ? ADJ_PLAIN : precision == POLSAR_COMPENSATED ? ADJ_COMP : ADJ_WIDE)
+                                    : (precision == POLSAR_PLAIN ? CHOL_PLAIN : precision == POLSAR_COMPENSATED ? CHOL_COMP : CHOL_WIDE);
+  b->block = block;
+  b->nt = cfg.nontemporal;
+  b->total_tiles = tiles;
+  const int gpc = grid_per_cu > 0 ? grid_per_cu : 8;
+  b->grid = (int)std::min<int64_t>(tiles, (int64_t)gpc * device_cus_b());
+  if (hipMalloc((void**)&b->d_img, sizeof(ImgDesc) * count) != hipSuccess) { release(b); return POLSAR_E_HIP; }
+  if (hipMalloc((void**)&b->d_partial, sizeof(double) * tiles) != hipSuccess) { release(b); return POLSAR_E_HIP; }
+  if (hipMemcpy(b->d_img, h.data(), sizeof(ImgDesc) * count, hipMemcpyHostToDevice) != hipSuccess) {
+    release(b);
+    return POLSAR_E_HIP;
+  }
+  b->args = BatchArgs{b->d_img, count, tiles, b->d_partial, grad_loss, counters,
+                      (ops & POLSAR_OP_INV_DET) ? 1 : 0, (ops & POLSAR_OP_WISHART_FWD) ? 1 : 0,
+                      (ops & POLSAR_OP_WISHART_BWD) ? 1 : 0};
+  // capture the kernels once
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { release(b); return POLSAR_E_HIP; }
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t e1 = enqueue(b, cs);
+    e = hipStreamEndCapture(cs, &b->graph);
+    if (e == hipSuccess) e = e1;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess) { release(b); return POLSAR_E_HIP; }
+  *out = b;
+  return POLSAR_OK;
+}
+
+int polsar_batch_run(polsar_batch* b, void* stream) {
+  if (!b || !b->exec) return POLSAR_E_ARG;
+  return hipGraphLaunch(b->exec, (hipStream_t)stream) == hipSuccess ? POLSAR_OK : POLSAR_E_HIP;
+}
+
+int polsar_batch_run_eager(polsar_batch* b, void* stream) {
+  if (!b) return POLSAR_E_ARG;
+  return enqueue(b, (hipStream_t)stream) == hipSuccess ? POLSAR_OK : POLSAR_E_HIP;
+}
+
+int64_t polsar_batch_tiles(const polsar_batch* b) { return b ? b->total_tiles : -1; }
+
+void polsar_batch_destroy(polsar_batch* b) { release(b); }
+
+}  // extern "C"

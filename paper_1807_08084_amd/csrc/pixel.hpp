@@ -1,0 +1,416 @@
+// Per-pixel arithmetic of the 3x3 Hermitian inverse and determinant.
+//
+// Packed layout of one matrix (Section 2.1, "Preliminaries and Notation"):
+// the upper triangle a, d, f (real diagonal) and b, c, e (complex), held as
+//   z[0]=a z[1]=d z[2]=f z[3]=Re b z[4]=Im b z[5]=Re c z[6]=Im c z[7]=Re e z[8]=Im e
+// The inverse is returned in the same packing.
+//
+// Every function here is __host__ __device__ so the same source can be
+// compiled for the host and exercised by logic tests; the kernels in
+// polsar.hip inline them.
+#pragma once
+
+#include <math.h>
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#define PX_HD __host__ __device__ __forceinline__
+#else
+#define PX_HD inline
+#endif
+
+namespace px {
+
+// Per-pixel status, also the values of the optional status plane.
+enum : int { ST_OK = 0, ST_REROUTED = 1, ST_NOT_PD = 2, ST_NONFINITE = 3 };
+
+PX_HD float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+PX_HD double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+PX_HD float abs_(float x) { return __builtin_fabsf(x); }
+PX_HD double abs_(double x) { return __builtin_fabs(x); }
+// Correctly rounded square root; natural logarithm from the math library.
+PX_HD float sqrt_(float x) { return sqrtf(x); }
+PX_HD double sqrt_(double x) { return sqrt(x); }
+PX_HD float log_(float x) { return logf(x); }
+PX_HD double log_(double x) { return log(x); }
+template <class T> PX_HD bool finite_(T x) { return __builtin_isfinite(x); }
+
+template <class T> struct Eps;
+template <> struct Eps<float> { static constexpr double u = 5.9604644775390625e-08; };   // 2^-24
+template <> struct Eps<double> { static constexpr double u = 1.1102230246251565e-16; };  // 2^-53
+
+// ---------------------------------------------------------------------------
+// Alg. 2 (Section 3.1), evaluated directly.
+// Cofactors from Eq. (adjoint_elements), split into real parts:
+//   a_c = d f - |e|^2                  d_c = a f - |c|^2        f_c = a d - |b|^2
+//   b_c = c conj(e) - b f   ->  Re: cr er + ci ei - br f     Im: ci er - cr ei - bi f
+//   c_c = b e - c d         ->  Re: br er - bi ei - cr d     Im: br ei + bi er - ci d
+//   e_c = c conj(b) - a e   ->  Re: cr br + ci bi - a er     Im: ci br - cr bi - a ei
+// Determinant from the real-part expansion along row 0 (Eq. detr):
+//   det = a a_c + Re b Re b_c + Im b Im b_c + Re c Re c_c + Im c Im c_c
+// then t = 1/det (the one division) and A^{-1} = t * adj(A) (Eq. inv_adjoint).
+// ---------------------------------------------------------------------------
+template <class T>
+PX_HD void cofactors_plain(const T z[9], T c[9]) {
+  const T a = z[0], d = z[1], f = z[2], br = z[3], bi = z[4], cr = z[5], ci = z[6], er = z[7], ei = z[8];
+  c[0] = d * f - (er * er + ei * ei);
+  c[1] = a * f - (cr * cr + ci * ci);
+  c[2] = a * d - (br * br + bi * bi);
+  c[3] = cr * er + ci * ei - br * f;
+  c[4] = ci * er - cr * ei - bi * f;
+  c[5] = br * er - bi * ei - cr * d;
+  c[6] = br * ei + bi * er - ci * d;
+  c[7] = cr * br + ci * bi - a * er;
+  c[8] = ci * br - cr * bi - a * ei;
+}
+
+template <class T>
+PX_HD T det_from_cofactors(const T z[9], const T c[9]) {
+  return z[0] * c[0] + z[3] * c[3] + z[4] * c[4] + z[5] * c[5] + z[6] * c[6];
+}
+
+// Classify an evaluated pixel: non-finite beats not-positive-definite.
+template <class T>
+PX_HD int classify(T det, T t) {
+  if (!finite_(det)) return ST_NONFINITE;
+  if (!(det > T(0))) return ST_NOT_PD;
+  if (!finite_(t)) return ST_NONFINITE;
+  return ST_OK;
+}
+
+template <class T>
+PX_HD int adjugate_plain(const T z[9], T x[9], T& det) {
+  T c[9];
+  cofactors_plain(z, c);
+  det = det_from_cofactors(z, c);
+  const T t = T(1) / det;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) x[k] = t * c[k];
+  return classify(det, t);
+}
+
+// FP32 storage, FP64 arithmetic: the same formulas on exactly widened inputs.
+PX_HD int adjugate_wide(const float z[9], float x[9], float& det) {
+  double zd[9], xd[9], dd;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) zd[k] = (double)z[k];
+  int st = adjugate_plain(zd, xd, dd);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) x[k] = (float)xd[k];
+  det = (float)dd;
+  const float t = 1.0f / det;
+  int st32 = classify(det, t);
+  return st32 > st ? st32 : st;
+}
+
+// ---------------------------------------------------------------------------
+// Compensated evaluation of the same formulas.
+// Each cofactor component is a signed dot product of three products, taken
+// with the Dot2 scheme of Ogita, Rump and Oishi ("Accurate sum and dot
+// product", SIAM J. Sci. Comput. 26(6), 2005, Alg. 5.3): error-free products
+// by FMA (TwoProduct) and error-free additions (TwoSum), the rounding errors
+// gathered in a second word.  The result is kept as an unevaluated pair
+// hi + lo with |hi + lo - exact| <= gamma_3^2 * sum|products|.
+// The determinant is the Dot2 sum of the five products a*a_c.hi, ...; the
+// five products with the low words are added into its error word.
+// FP contraction is disabled here: every fused operation is explicit.
+// ---------------------------------------------------------------------------
+template <class T> struct DW { T hi, lo; };
+
+template <class T>
+PX_HD void two_sum(T a, T b, T& s, T& e) {
+#if defined(__clang__)
+#pragma clang fp contract(off)
+#endif
+  s = a + b;
+  const T bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Dot2 of (x1 y1 + x2 y2 + x3 y3); also returns sum|x_k y_k| (rounded).
+template <class T>
+PX_HD DW<T> dot3(T x1, T y1, T x2, T y2, T x3, T y3, T& mag) {
+#if defined(__clang__)
+#pragma clang fp contract(off)
+#endif
+  T p = x1 * y1;
+  T s = fma_(x1, y1, -p);
+  T h = x2 * y2;
+  T r = fma_(x2, y2, -h);
+  T q;
+  mag = abs_(p) + abs_(h);
+  two_sum(p, h, p, q);
+  s = s + (q + r);
+  h = x3 * y3;
+  r = fma_(x3, y3, -h);
+  mag = mag + abs_(h);
+  two_sum(p, h, p, q);
+  s = s + (q + r);
+  return DW<T>{p, s};
+}
+
+template <class T>
+PX_HD void cofactors_comp(const T z[9], DW<T> c[9], T mag[9]) {
+  const T a = z[0], d = z[1], f = z[2], br = z[3], bi = z[4], cr = z[5], ci = z[6], er = z[7], ei = z[8];
+  c[0] = dot3(d, f, -er, er, -ei, ei, mag[0]);
+  c[1] = dot3(a, f, -cr, cr, -ci, ci, mag[1]);
+  c[2] = dot3(a, d, -br, br, -bi, bi, mag[2]);
+  c[3] = dot3(cr, er, ci, ei, -br, f, mag[3]);
+  c[4] = dot3(ci, er, -cr, ei, -bi, f, mag[4]);
+  c[5] = dot3(br, er, -bi, ei, -cr, d, mag[5]);
+  c[6] = dot3(br, ei, bi, er, -ci, d, mag[6]);
+  c[7] = dot3(cr, br, ci, bi, -a, er, mag[7]);
+  c[8] = dot3(ci, br, -cr, bi, -a, ei, mag[8]);
+}
+
+// Compensated determinant from the row-0 expansion; returns the rounded det
+// and the a-posteriori bound E >= |det_returned - det(A)| where
+//   E = (1 + 64u) [ u|det| + 64u^2 sum|x_i hi_i| + 40u^2 sum|x_i| S_i ],
+// x = (a, Re b, Im b, Re c, Im c), S_i = sum|products| of cofactor i.
+// Constants: the five-term Dot2 contributes gamma_5^2 + gamma_5 gamma_6
+// (<= 56u^2) on sum|x_i hi_i|; the low words (|lo_i| <= gamma_4 S_i) added
+// with gamma_6 give 24u^2 on sum|x_i| S_i, the cofactors' own Dot2 errors
+// gamma_3^2 (<= 9u^2) on the same sum; the final rounding u|det|.  All
+// rounded up, with a (1 + 64u) margin for evaluating E itself.
+template <class T>
+PX_HD T det_comp(const T z[9], const DW<T> c[9], const T mag[9], T& bound) {
+#if defined(__clang__)
+#pragma clang fp contract(off)
+#endif
+  const T x[5] = {z[0], z[3], z[4], z[5], z[6]};
+  const int idx[5] = {0, 3, 4, 5, 6};
+  T p = x[0] * c[0].hi;
+  T s = fma_(x[0], c[0].hi, -p);
+  T A = abs_(p);
+  T C = abs_(x[0]) * mag[0];
+#pragma unroll
+  for (int i = 1; i < 5; ++i) {
+    const T h = x[i] * c[idx[i]].hi;
+    const T r = fma_(x[i], c[idx[i]].hi, -h);
+    T q;
+    A = A + abs_(h);
+    C = fma_(abs_(x[i]), mag[idx[i]], C);
+    two_sum(p, h, p, q);
+    s = s + (q + r);
+  }
+#pragma unroll
+  for (int i = 0; i < 5; ++i) s = fma_(x[i], c[idx[i]].lo, s);
+  const T det = p + s;
+  constexpr T u = (T)Eps<T>::u;
+  constexpr T u2 = (T)(Eps<T>::u * Eps<T>::u);
+  bound = (T(1) + T(64) * u) * (u * abs_(det) + (T(64) * u2) * A + (T(40) * u2) * C);
+  return det;
+}
+
+template <class T>
+PX_HD void scale_comp(const DW<T> c[9], T t, T x[9]) {
+#if defined(__clang__)
+#pragma clang fp contract(off)
+#endif
+#pragma unroll
+  for (int k = 0; k < 9; ++k) x[k] = fma_(c[k].hi, t, c[k].lo * t);
+}
+
+// Compensated FP64 (no reroute: FP64 is the widest type on the path).
+PX_HD int adjugate_comp(const double z[9], double x[9], double& det) {
+  DW<double> c[9];
+  double mag[9], bound;
+  cofactors_comp(z, c, mag);
+  det = det_comp(z, c, mag, bound);
+  const double t = 1.0 / det;
+  scale_comp(c, t, x);
+  return classify(det, t);
+}
+
+// Relative threshold on the determinant bound above which an FP32 pixel is
+// recomputed in FP64.
+constexpr float REROUTE_REL = 1e-6f;
+
+// Compensated FP32 with selective FP64 recompute.  A pixel whose bound
+// exceeds REROUTE_REL * |det|, or whose det is not positive or not finite,
+// is recomputed by the compensated FP64 path from its exactly widened
+// inputs and rounded to FP32 (status ST_REROUTED when that succeeds).
+PX_HD int adjugate_comp(const float z[9], float x[9], float& det, float* bound_out = nullptr) {
+  DW<float> c[9];
+  float mag[9], bound;
+  cofactors_comp(z, c, mag);
+  det = det_comp(z, c, mag, bound);
+  if (bound_out) *bound_out = bound;
+  const float t = 1.0f / det;
+  const bool ok = det > 0.0f && finite_(det) && finite_(t) && !(bound > REROUTE_REL * det);
+  if (ok) {
+    scale_comp(c, t, x);
+    return ST_OK;
+  }
+  double zd[9], xd[9], dd;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) zd[k] = (double)z[k];
+  int st = adjugate_comp(zd, xd, dd);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) x[k] = (float)xd[k];
+  det = (float)dd;
+  if (st == ST_OK) {
+    st = classify(det, 1.0f / det);
+    if (st == ST_OK) st = ST_REROUTED;
+  }
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky comparison form (Section 2.2 and Alg. 1): A = L L^H,
+//   l00 = sqrt(a), v0 = 1/l00, l10 = conj(b) v0, l20 = conj(c) v0,
+//   l11 = sqrt(d - |l10|^2), v1 = 1/l11,
+//   l21 = (conj(e) - l20 conj(l10)) v1   (the conjugate of the printed
+//                                          assignment, which solves A[1][2]
+//                                          instead of A[2][1]),
+//   l22 = sqrt(f - |l20|^2 - |l21|^2), v2 = 1/l22;
+// T = L^{-1}: t10 = -l10 v0 v1, t20 = v2 v0 (l21 l10 v1 - l20), t21 = -l21 v1 v2;
+// det = (l00 l11 l22)^2 and A^{-1} = T^H T (upper triangle).
+// Status: non-finite input first, then not positive definite when a squared
+// pivot is <= 0, then non-finite results.
+// ---------------------------------------------------------------------------
+template <class T>
+PX_HD int cholesky_plain(const T z[9], T x[9], T& det) {
+  const T a = z[0], d = z[1], f = z[2], br = z[3], bi = z[4], cr = z[5], ci = z[6], er = z[7], ei = z[8];
+  const T p0 = a;
+  const T l00 = sqrt_(p0), v0 = T(1) / l00;
+  const T l10r = br * v0, l10i = -bi * v0;  // conj(b) v0
+  const T l20r = cr * v0, l20i = -ci * v0;  // conj(c) v0
+  const T p1 = d - (l10r * l10r + l10i * l10i);
+  const T l11 = sqrt_(p1), v1 = T(1) / l11;
+  // l20 conj(l10)
+  const T mr = l20r * l10r + l20i * l10i;
+  const T mi = l20i * l10r - l20r * l10i;
+  const T l21r = (er - mr) * v1, l21i = (-ei - mi) * v1;
+  const T p2 = f - (l20r * l20r + l20i * l20i) - (l21r * l21r + l21i * l21i);
+  const T l22 = sqrt_(p2), v2 = T(1) / l22;
+  const T t10s = -v0 * v1;
+  const T t10r = l10r * t10s, t10i = l10i * t10s;
+  // l21 l10 v1 - l20
+  const T wr = (l21r * l10r - l21i * l10i) * v1 - l20r;
+  const T wi = (l21r * l10i + l21i * l10r) * v1 - l20i;
+  const T t20s = v2 * v0;
+  const T t20r = wr * t20s, t20i = wi * t20s;
+  const T t21s = -v1 * v2;
+  const T t21r = l21r * t21s, t21i = l21i * t21s;
+  const T g = l00 * l11 * l22;
+  det = g * g;
+  x[0] = v0 * v0 + (t10r * t10r + t10i * t10i) + (t20r * t20r + t20i * t20i);
+  x[1] = v1 * v1 + (t21r * t21r + t21i * t21i);
+  x[2] = v2 * v2;
+  // b_i = conj(t10) t11 + conj(t20) t21
+  x[3] = t10r * v1 + (t20r * t21r + t20i * t21i);
+  x[4] = -t10i * v1 + (t20r * t21i - t20i * t21r);
+  // c_i = conj(t20) t22, e_i = conj(t21) t22
+  x[5] = t20r * v2;
+  x[6] = -t20i * v2;
+  x[7] = t21r * v2;
+  x[8] = -t21i * v2;
+  bool finite_in = true;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) finite_in = finite_in && finite_(z[k]);
+  if (!finite_in) return ST_NONFINITE;
+  if (p0 <= T(0) || p1 <= T(0) || p2 <= T(0)) return ST_NOT_PD;
+  if (!(finite_(det) && finite_(v0) && finite_(v1) && finite_(v2) && finite_(p0 + p1 + p2)))
+    return ST_NONFINITE;
+  return ST_OK;
+}
+
+PX_HD int cholesky_wide(const float z[9], float x[9], float& det) {
+  double zd[9], xd[9], dd;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) zd[k] = (double)z[k];
+  int st = cholesky_plain(zd, xd, dd);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) x[k] = (float)xd[k];
+  det = (float)dd;
+  if (st == ST_OK && !(finite_(det) && det > 0.0f && finite_(1.0f / det))) st = ST_NONFINITE;
+  return st;
+}
+
+// FP32 Cholesky with an FP64 recompute of pixels whose FP32 pivots fail.
+PX_HD int cholesky_fallback(const float z[9], float x[9], float& det) {
+  int st = cholesky_plain(z, x, det);
+  if (st == ST_OK) return ST_OK;
+  st = cholesky_wide(z, x, det);
+  return st == ST_OK ? ST_REROUTED : st;
+}
+
+// ---------------------------------------------------------------------------
+// Wishart term for one pixel: l = N (ln det S + tr(S^{-1} Z)), with S^{-1}
+// from Alg. 2 (adjugate over det) and
+//   tr(adj(S) Z) = a_c z_a + d_c z_d + f_c z_f
+//                  + 2 (Re b_c Re z_b + Im b_c Im z_b + ... for c and e),
+// since the off-diagonal pairs of a product of Hermitian matrices add to
+// twice a real part.
+// Gradient with respect to the packed real parameters of S:
+//   M = N (P - P Z P), P = S^{-1} recomputed from the adjugate,
+//   grad = g (M00, M11, M22, 2Re M01, 2Im M01, 2Re M02, 2Im M02, 2Re M12, 2Im M12)
+// (dl = tr(M dS) for Hermitian M and dS; g is the upstream gradient).
+// ---------------------------------------------------------------------------
+template <class T>
+PX_HD int wishart_pixel(const T s[9], const T z[9], T n_looks, T* ell, T* grad, T gscale) {
+  T c[9];
+  cofactors_plain(s, c);
+  const T det = det_from_cofactors(s, c);
+  const T t = T(1) / det;
+  const int st = classify(det, t);
+  if (ell) {
+    const T tr = c[0] * z[0] + c[1] * z[1] + c[2] * z[2] +
+                 T(2) * (c[3] * z[3] + c[4] * z[4] + c[5] * z[5] + c[6] * z[6] + c[7] * z[7] + c[8] * z[8]);
+    // log of the rounded det; the caller has chosen the precision
+    *ell = n_looks * (log_(det) + tr * t);
+  }
+  if (grad) {
+    // P = t * adj(S) as a full Hermitian matrix: P00..P22 real, P01, P02, P12 complex
+    T P[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) P[k] = t * c[k];
+    // W = Z P (full 3x3 complex), then Q = P W (upper triangle only)
+    // Hermitian entries: H(i,j) with H(j,i) = conj(H(i,j)).
+    T Zr[3][3], Zi[3][3], Pr[3][3], Pi[3][3];
+    auto fill = [](const T* v, T (&R)[3][3], T (&I)[3][3]) {
+      R[0][0] = v[0]; I[0][0] = 0; R[1][1] = v[1]; I[1][1] = 0; R[2][2] = v[2]; I[2][2] = 0;
+      R[0][1] = v[3]; I[0][1] = v[4]; R[1][0] = v[3]; I[1][0] = -v[4];
+      R[0][2] = v[5]; I[0][2] = v[6]; R[2][0] = v[5]; I[2][0] = -v[6];
+      R[1][2] = v[7]; I[1][2] = v[8]; R[2][1] = v[7]; I[2][1] = -v[8];
+    };
+    fill(z, Zr, Zi);
+    fill(P, Pr, Pi);
+    T Wr[3][3], Wi[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        T sr = 0, si = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          sr += Zr[i][k] * Pr[k][j] - Zi[i][k] * Pi[k][j];
+          si += Zr[i][k] * Pi[k][j] + Zi[i][k] * Pr[k][j];
+        }
+        Wr[i][j] = sr;
+        Wi[i][j] = si;
+      }
+    const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
+    const T gs = gscale * n_looks;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const int i = ii[q], j = jj[q];
+      T qr = 0, qi = 0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        qr += Pr[i][k] * Wr[k][j] - Pi[i][k] * Wi[k][j];
+        qi += Pr[i][k] * Wi[k][j] + Pi[i][k] * Wr[k][j];
+      }
+      if (q < 3) {
+        grad[q] = gs * (Pr[i][j] - qr);
+      } else {
+        grad[3 + 2 * (q - 3)] = T(2) * gs * (Pr[i][j] - qr);
+        grad[4 + 2 * (q - 3)] = T(2) * gs * (Pi[i][j] - qi);
+      }
+    }
+  }
+  return st;
+}
+
+}  // namespace px

@@ -1,0 +1,613 @@
+// HIP kernels and C ABI for gfx950: per-pixel 3x3 Hermitian inverse and
+// determinant (Alg. 2; Alg. 1 for comparison) and the Wishart term.
+//
+// Every op is bandwidth-bound streaming over structure-of-arrays planes:
+// one lane owns V consecutive pixels (V = 16 bytes / element size, so each
+// plane access is one 128-bit global load or store), U such vectors per tile
+// per lane, and a tile is block*U vectors.  A lane issues all of its 9*U
+// (or 18*U) loads before any arithmetic, then all of its stores.  Pixels are
+// independent; nothing is shared between lanes except the fixed-order
+// reductions of the Wishart sum and the status counters.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/polsar.h"
+#include "common.hpp"
+
+namespace {
+using namespace polsar_dev;
+
+struct InvDetArgs {
+  const void* z;
+  int64_t zp;
+  void* inv;
+  int64_t ip;
+  void* det;
+  uint8_t* status;
+  unsigned long long* counters;
+  int64_t n;      // pixels
+  int64_t nvec;   // full vectors: n / V
+  int64_t tiles;  // ceil(nvec / (block * U)), at least 1
+};
+
+// One pixel-vector of the inverse/determinant: load done by the caller.
+template <class T, int OP, int V, bool NT>
+__device__ __forceinline__ void inv_det_vec(const InvDetArgs& a, const T (&in)[9][V], int64_t v,
+                                            unsigned& c0, unsigned& c1, unsigned& c2) {
+  T out[9][V], dt[V];
+  int st[V];
+#pragma unroll
+  for (int l = 0; l < V; ++l) {
+    T zz[9], xx[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) zz[k] = in[k][l];
+    st[l] = run_pixel<T, OP>(zz, xx, dt[l]);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) out[k][l] = xx[k];
+    tally(st[l], c0, c1, c2);
+  }
+  const int64_t e = v * V;
+  if (a.inv) {
+    T* inv = (T*)a.inv;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) store_v<T, V, NT>(inv + k * a.ip + e, out[k]);
+  }
+  if (a.det) store_v<T, V, NT>((T*)a.det + e, dt);
+  if (a.status) store_status<V>(a.status + e, st);
+}
+
+template <class T, int OP, int V, int U, bool NT>
+__global__ __launch_bounds__(256) void k_inv_det(InvDetArgs a) {
+  const T* __restrict__ z = (const T*)a.z;
+  const int B = blockDim.x;
+  unsigned c0 = 0, c1 = 0, c2 = 0;
+  for (int64_t tile = blockIdx.x; tile < a.tiles; tile += gridDim.x) {
+    const int64_t v0 = tile * (int64_t)(B * U) + threadIdx.x;
+    T in[U][9][V];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t v = v0 + (int64_t)u * B;
+      if (v < a.nvec) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) load_v<T, V, NT>(z + k * a.zp + v * V, in[u][k]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t v = v0 + (int64_t)u * B;
+      if (v < a.nvec) inv_det_vec<T, OP, V, NT>(a, in[u], v, c0, c1, c2);
+    }
+    if (V > 1 && tile == a.tiles - 1) {
+      // the n mod V pixels after the last full vector, one per lane
+      const int64_t i = a.nvec * V + threadIdx.x;
+      if (i < a.n) {
+        T zz[9], xx[9], dt;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) zz[k] = z[k * a.zp + i];
+        const int st = run_pixel<T, OP>(zz, xx, dt);
+        tally(st, c0, c1, c2);
+        if (a.inv)
+#pragma unroll
+          for (int k = 0; k < 9; ++k) ((T*)a.inv)[k * a.ip + i] = xx[k];
+        if (a.det) ((T*)a.det)[i] = dt;
+        if (a.status) a.status[i] = (uint8_t)st;
+      }
+    }
+  }
+  if (a.counters) flush_counters(a.counters, c0, c1, c2);
+}
+
+// ------------------------------------------------------------------ Wishart
+struct WishartArgs {
+  const void* s;
+  int64_t sp;
+  const void* z;
+  int64_t zp;
+  double n_looks;
+  void* ell;
+  double* partial;  // one FP64 partial sum per tile (forward)
+  const double* grad_loss;
+  void* grad;
+  int64_t gp;
+  unsigned long long* counters;
+  int64_t n, nvec, tiles;
+  int fwd, bwd;
+};
+
+template <class T, int V, bool NT>
+__device__ __forceinline__ double wishart_vec(const WishartArgs& a, const T (&s)[9][V], const T (&z)[9][V],
+                                              int64_t v, T gscale, unsigned& c0, unsigned& c2) {
+  T ell[V], g[9][V];
+  double acc = 0.0;
+  unsigned dummy = 0;
+#pragma unroll
+  for (int l = 0; l < V; ++l) {
+    T ss[9], zz[9], gg[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) { ss[k] = s[k][l]; zz[k] = z[k][l]; }
+    const int st = px::wishart_pixel<T>(ss, zz, (T)a.n_looks, a.fwd ? &ell[l] : nullptr,
+                                        a.bwd ? gg : nullptr, gscale);
+    tally(st, c0, dummy, c2);
+    if (a.fwd) acc += (double)ell[l];
+    if (a.bwd)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) g[k][l] = gg[k];
+  }
+  const int64_t e = v * V;
+  if (a.fwd && a.ell) store_v<T, V, NT>((T*)a.ell + e, ell);
+  if (a.bwd) {
+    T* gp = (T*)a.grad;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) store_v<T, V, NT>(gp + k * a.gp + e, g[k]);
+  }
+  return acc;
+}
+
+template <class T, int V, int U, bool NT>
+__global__ __launch_bounds__(256) void k_wishart(WishartArgs a) {
+  const T* __restrict__ S = (const T*)a.s;
+  const T* __restrict__ Z = (const T*)a.z;
+  const int B = blockDim.x;
+  const T gscale = a.bwd ? (a.grad_loss ? (T)*a.grad_loss : T(1)) : T(1);
+  unsigned c0 = 0, c2 = 0;
+  for (int64_t tile = blockIdx.x; tile < a.tiles; tile += gridDim.x) {
+    const int64_t v0 = tile * (int64_t)(B * U) + threadIdx.x;
+    T s[U][9][V], z[U][9][V];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t v = v0 + (int64_t)u * B;
+      if (v < a.nvec) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) load_v<T, V, NT>(S + k * a.sp + v * V, s[u][k]);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) load_v<T, V, NT>(Z + k * a.zp + v * V, z[u][k]);
+      }
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t v = v0 + (int64_t)u * B;
+      if (v < a.nvec) acc += wishart_vec<T, V, NT>(a, s[u], z[u], v, gscale, c0, c2);
+    }
+    if (V > 1 && tile == a.tiles - 1) {
+      const int64_t i = a.nvec * V + threadIdx.x;
+      if (i < a.n) {
+        T ss[9], zz[9], gg[9], el;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) { ss[k] = S[k * a.sp + i]; zz[k] = Z[k * a.zp + i]; }
+        unsigned dummy = 0;
+        const int st = px::wishart_pixel<T>(ss, zz, (T)a.n_looks, a.fwd ? &el : nullptr,
+                                            a.bwd ? gg : nullptr, gscale);
+        tally(st, c0, dummy, c2);
+        if (a.fwd) {
+          acc += (double)el;
+          if (a.ell) ((T*)a.ell)[i] = el;
+        }
+        if (a.bwd)
+#pragma unroll
+          for (int k = 0; k < 9; ++k) ((T*)a.grad)[k * a.gp + i] = gg[k];
+      }
+    }
+    if (a.fwd) {
+      const double bs = block_sum(acc);
+      if (threadIdx.x == 0) a.partial[tile] = bs;
+    }
+  }
+  if (a.counters) flush_counters(a.counters, c0, 0u, c2);
+}
+
+// Fixed-order sum of `count` partials into *out (one block of 256 lanes).
+__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partial, int64_t count,
+                                                double* __restrict__ out) {
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += blockDim.x) s += partial[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) *out = s;
+}
+
+// ------------------------------------------------------------------ copy probe
+template <class T, int V, int NI, int NO>
+__global__ __launch_bounds__(256) void k_copy(const T* __restrict__ src, int64_t sp, T* __restrict__ dst,
+                                              int64_t dp, int64_t nvec, int64_t n) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < nvec) {
+    T in[NI][V];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) load_v<T, V, true>(src + k * sp + v * V, in[k]);
+#pragma unroll
+    for (int k = 0; k < NO; ++k) store_v<T, V, true>(dst + k * dp + v * V, in[k % NI]);
+  }
+  if (blockIdx.x == 0) {
+    const int64_t i = nvec * V + threadIdx.x;
+    if (i < n)
+      for (int k = 0; k < NO; ++k) dst[k * dp + i] = src[(k % NI) * sp + i];
+  }
+}
+
+// ------------------------------------------------------------------ host side
+std::mutex g_mu;
+std::map<std::tuple<int, int, int, int>, polsar_launch> g_cfg;
+
+polsar_launch default_launch(int op, int dtype, int method, int prec) {
+  (void)method;
+  (void)prec;
+  if (op == 1) return polsar_launch{256, 1, 0, 1};
+  return polsar_launch{256, dtype == POLSAR_F32 ? 1 : 2, 0, 1};
+}
+
+polsar_launch get_cfg(int op, int dtype, int method, int prec) {
+  std::lock_guard<std::mutex> g(g_mu);
+  auto it = g_cfg.find(std::make_tuple(op, dtype, method, prec));
+  return it == g_cfg.end() ? default_launch(op, dtype, method, prec) : it->second;
+}
+
+bool valid_launch(const polsar_launch& c, int op) {
+  if (c.block != 64 && c.block != 128 && c.block != 256) return false;
+  if (c.unroll != 1 && c.unroll != 2 && !(op == 0 && c.unroll == 4)) return false;
+  if (c.grid_per_cu < 0 || c.grid_per_cu > 64) return false;
+  if (c.nontemporal != 0 && c.nontemporal != 1) return false;
+  return true;
+}
+
+int device_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
+    cached[dev] = cu;
+  }
+  return cached[dev];
+}
+
+inline size_t esize(int dtype) { return dtype == POLSAR_F64 ? 8 : 4; }
+
+// Byte range [lo, hi) spanned by `planes` planes of n elements at `pitch`.
+struct Range {
+  uintptr_t lo, hi;
+};
+Range span(const void* p, int planes, int64_t pitch, int64_t n, size_t es) {
+  uintptr_t lo = (uintptr_t)p;
+  return Range{lo, lo + (uintptr_t)(((planes - 1) * pitch + n) * (int64_t)es)};
+}
+bool overlap(Range a, Range b) { return a.lo < b.hi && b.lo < a.hi; }
+
+int check_planes(const void* p, int64_t pitch, int64_t n, size_t es) {
+  if (!p) return n == 0 ? POLSAR_OK : POLSAR_E_ARG;  // an empty batch may pass null planes
+  if (pitch < n || pitch > ((int64_t)1 << 40)) return POLSAR_E_ARG;
+  if ((uintptr_t)p % es) return POLSAR_E_ALIGN;
+  return POLSAR_OK;
+}
+
+bool vec_ok(const void* p, int64_t pitch, size_t es) {
+  return p == nullptr || (((uintptr_t)p % 16) == 0 && ((pitch * (int64_t)es) % 16) == 0);
+}
+
+int op_code(int method, int prec) {
+  if (method == POLSAR_ADJUGATE) return prec == POLSAR_PLAIN ? ADJ_PLAIN : prec == POLSAR_COMPENSATED ? ADJ_COMP : ADJ_WIDE;
+  return prec == POLSAR_PLAIN ? CHOL_PLAIN : prec == POLSAR_COMPENSATED ? CHOL_COMP : CHOL_WIDE;
+}
+
+// Launch helpers: pick the template instance for (V, U, NT).
+template <class T, int OP, int V, int U>
+hipError_t go_inv_det(const polsar_launch& c, int64_t grid, InvDetArgs& a, hipStream_t s) {
+  if (c.nontemporal)
+    hipLaunchKernelGGL((k_inv_det<T, OP, V, U, true>), dim3((unsigned)grid), dim3(c.block), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_inv_det<T, OP, V, U, false>), dim3((unsigned)grid), dim3(c.block), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class T, int OP>
+hipError_t dispatch_inv_det(const polsar_launch& c, bool vec, InvDetArgs& a, hipStream_t s) {
+  constexpr int VW = 16 / sizeof(T);
+  const int V = vec ? VW : 1;
+  a.nvec = a.n / V;
+  const int64_t per_tile = (int64_t)c.block * c.unroll;
+  a.tiles = std::max<int64_t>(1, (a.nvec + per_tile - 1) / per_tile);
+  int64_t grid = a.tiles;
+  if (c.grid_per_cu > 0) grid = std::min<int64_t>(grid, (int64_t)c.grid_per_cu * device_cus());
+  if (vec) {
+    if (c.unroll == 1) return go_inv_det<T, OP, VW, 1>(c, grid, a, s);
+    if (c.unroll == 2) return go_inv_det<T, OP, VW, 2>(c, grid, a, s);
+    return go_inv_det<T, OP, VW, 4>(c, grid, a, s);
+  }
+  if (c.unroll == 1) return go_inv_det<T, OP, 1, 1>(c, grid, a, s);
+  if (c.unroll == 2) return go_inv_det<T, OP, 1, 2>(c, grid, a, s);
+  return go_inv_det<T, OP, 1, 4>(c, grid, a, s);
+}
+
+hipError_t launch_inv_det(int dtype, int op, const polsar_launch& c, bool vec, InvDetArgs& a, hipStream_t s) {
+  if (dtype == POLSAR_F32) {
+    switch (op) {
+      case ADJ_PLAIN: return dispatch_inv_det<float, ADJ_PLAIN>(c, vec, a, s);
+      case ADJ_COMP: return dispatch_inv_det<float, ADJ_COMP>(c, vec, a, s);
+      case ADJ_WIDE: return dispatch_inv_det<float, ADJ_WIDE>(c, vec, a, s);
+      case CHOL_PLAIN: return dispatch_inv_det<float, CHOL_PLAIN>(c, vec, a, s);
+      case CHOL_COMP: return dispatch_inv_det<float, CHOL_COMP>(c, vec, a, s);
+      default: return dispatch_inv_det<float, CHOL_WIDE>(c, vec, a, s);
+    }
+  }
+  switch (op) {
+    case ADJ_PLAIN: return dispatch_inv_det<double, ADJ_PLAIN>(c, vec, a, s);
+    case ADJ_COMP: return dispatch_inv_det<double, ADJ_COMP>(c, vec, a, s);
+    default: return dispatch_inv_det<double, CHOL_PLAIN>(c, vec, a, s);
+  }
+}
+
+// Validates polsar_inv_det arguments; fills `a` and `vec` on success.
+int prepare_inv_det(int dtype, int method, int prec, int64_t n, const void* z, int64_t zp, void* inv,
+                    int64_t ip, void* det, uint8_t* status, unsigned long long* counters, InvDetArgs& a,
+                    bool& vec) {
+  if (dtype != POLSAR_F32 && dtype != POLSAR_F64) return POLSAR_E_ARG;
+  if (method != POLSAR_ADJUGATE && method != POLSAR_CHOLESKY) return POLSAR_E_ARG;
+  if (prec != POLSAR_PLAIN && prec != POLSAR_COMPENSATED && prec != POLSAR_WIDE) return POLSAR_E_ARG;
+  if (n < 0) return POLSAR_E_ARG;
+  if (dtype == POLSAR_F64 && prec == POLSAR_WIDE) return POLSAR_E_UNSUPPORTED;
+  if (dtype == POLSAR_F64 && method == POLSAR_CHOLESKY && prec != POLSAR_PLAIN) return POLSAR_E_UNSUPPORTED;
+  const size_t es = esize(dtype);
+  int r = check_planes(z, zp, n, es);
+  if (r) return r;
+  if (inv && (r = check_planes(inv, ip, n, es))) return r;
+  if (det && ((uintptr_t)det % es)) return POLSAR_E_ALIGN;
+  if (counters && ((uintptr_t)counters % 8)) return POLSAR_E_ALIGN;
+  if (!inv && !det && !status && !counters) return POLSAR_E_ARG;
+  if (n > 0) {
+    const Range rz = span(z, 9, zp, n, es);
+    if (inv) {
+      const Range ri = span(inv, 9, ip, n, es);
+      if (!(inv == z && ip == zp) && overlap(ri, rz)) return POLSAR_E_ALIAS;
+    }
+    if (det) {
+      const Range rd = span(det, 1, n, n, es);
+      if (overlap(rd, rz) || (inv && overlap(rd, span(inv, 9, ip, n, es)))) return POLSAR_E_ALIAS;
+    }
+    if (status) {
+      const Range rs = span(status, 1, n, n, 1);
+      if (overlap(rs, rz) || (inv && overlap(rs, span(inv, 9, ip, n, es))) || (det && overlap(rs, span(det, 1, n, n, es))))
+        return POLSAR_E_ALIAS;
+    }
+  }
+  a = InvDetArgs{z, zp, inv, ip, det, status, counters, n, 0, 0};
+  const int VW = (int)(16 / es);
+  vec = vec_ok(z, zp, es) && vec_ok(inv, ip, es) && vec_ok(det, 0, es) &&
+        (status == nullptr || ((uintptr_t)status % VW) == 0);
+  return POLSAR_OK;
+}
+
+// ---- Wishart launch
+template <class T, int V, int U>
+hipError_t go_wishart(const polsar_launch& c, int64_t grid, WishartArgs& a, hipStream_t s) {
+  if (c.nontemporal)
+    hipLaunchKernelGGL((k_wishart<T, V, U, true>), dim3((unsigned)grid), dim3(c.block), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_wishart<T, V, U, false>), dim3((unsigned)grid), dim3(c.block), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t dispatch_wishart(const polsar_launch& c, bool vec, WishartArgs& a, hipStream_t s) {
+  constexpr int VW = 16 / sizeof(T);
+  const int V = vec ? VW : 1;
+  a.nvec = a.n / V;
+  const int64_t per_tile = (int64_t)c.block * c.unroll;
+  a.tiles = std::max<int64_t>(1, (a.nvec + per_tile - 1) / per_tile);
+  int64_t grid = a.tiles;
+  if (c.grid_per_cu > 0) grid = std::min<int64_t>(grid, (int64_t)c.grid_per_cu * device_cus());
+  if (vec) return c.unroll == 1 ? go_wishart<T, VW, 1>(c, grid, a, s) : go_wishart<T, VW, 2>(c, grid, a, s);
+  return c.unroll == 1 ? go_wishart<T, 1, 1>(c, grid, a, s) : go_wishart<T, 1, 2>(c, grid, a, s);
+}
+
+int64_t max_wishart_tiles(int dtype, int64_t n) {
+  // smallest tile: 64 lanes x 1 vector of one element
+  (void)dtype;
+  return std::max<int64_t>(1, (n + 63) / 64);
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+struct polsar_batch;  // defined in batch.hip
+
+extern "C" {
+
+const char* polsar_version(void) { return "polsar-mi355x 0.1 (gfx950)"; }
+
+const char* polsar_status_string(int status) {
+  switch (status) {
+    case POLSAR_OK: return "ok";
+    case POLSAR_E_ARG: return "invalid argument";
+    case POLSAR_E_ALIGN: return "misaligned pointer";
+    case POLSAR_E_UNSUPPORTED: return "unsupported combination";
+    case POLSAR_E_HIP: return "HIP runtime error";
+    case POLSAR_E_WORKSPACE: return "workspace missing or too small";
+    case POLSAR_E_ALIAS: return "outputs overlap inputs";
+    default: return "unknown status";
+  }
+}
+
+int polsar_device_compute_units(int* cus) {
+  if (!cus) return POLSAR_E_ARG;
+  *cus = device_cus();
+  return POLSAR_OK;
+}
+
+int polsar_get_launch(int op, int dtype, int method, int precision, polsar_launch* out) {
+  if (!out || (op != 0 && op != 1)) return POLSAR_E_ARG;
+  *out = get_cfg(op, dtype, method, precision);
+  return POLSAR_OK;
+}
+
+int polsar_set_launch(int op, int dtype, int method, int precision, const polsar_launch* cfg) {
+  if (!cfg || (op != 0 && op != 1) || !valid_launch(*cfg, op)) return POLSAR_E_ARG;
+  std::lock_guard<std::mutex> g(g_mu);
+  g_cfg[std::make_tuple(op, dtype, method, precision)] = *cfg;
+  return POLSAR_OK;
+}
+
+int polsar_inv_det(int dtype, int method, int precision, int64_t n, const void* z, int64_t z_pitch, void* inv,
+                   int64_t inv_pitch, void* det, uint8_t* status, unsigned long long* counters, void* stream) {
+  InvDetArgs a;
+  bool vec = false;
+  int r = prepare_inv_det(dtype, method, precision, n, z, z_pitch, inv, inv_pitch, det, status, counters, a, vec);
+  if (r) return r;
+  if (n == 0) return POLSAR_OK;
+  const polsar_launch c = get_cfg(0, dtype, method, precision);
+  if (launch_inv_det(dtype, op_code(method, precision), c, vec, a, (hipStream_t)stream) != hipSuccess)
+    return POLSAR_E_HIP;
+  return POLSAR_OK;
+}
+
+size_t polsar_wishart_workspace_bytes(int dtype, int64_t n) {
+  if (n < 0) return 0;
+  return (size_t)max_wishart_tiles(dtype, n) * sizeof(double);
+}
+
+int polsar_wishart_loglik(int dtype, int pass, int64_t n, const void* sigma, int64_t s_pitch, const void* z,
+                          int64_t z_pitch, double n_looks, double* loss, void* ell, const double* grad_loss,
+                          void* grad, int64_t g_pitch, void* workspace, size_t ws_bytes,
+                          unsigned long long* counters, void* stream) {
+  if (dtype != POLSAR_F32 && dtype != POLSAR_F64) return POLSAR_E_ARG;
+  if (pass != POLSAR_FWD && pass != POLSAR_BWD && pass != POLSAR_FWD_BWD) return POLSAR_E_ARG;
+  if (n < 0 || !(n_looks > 0.0)) return POLSAR_E_ARG;
+  const bool fwd = pass & POLSAR_FWD, bwd = pass & POLSAR_BWD;
+  const size_t es = esize(dtype);
+  int r = check_planes(sigma, s_pitch, n, es);
+  if (r) return r;
+  if ((r = check_planes(z, z_pitch, n, es))) return r;
+  if (fwd && !loss) return POLSAR_E_ARG;
+  if (loss && ((uintptr_t)loss % 8)) return POLSAR_E_ALIGN;
+  if (grad_loss && ((uintptr_t)grad_loss % 8)) return POLSAR_E_ALIGN;
+  if (ell && ((uintptr_t)ell % es)) return POLSAR_E_ALIGN;
+  if (counters && ((uintptr_t)counters % 8)) return POLSAR_E_ALIGN;
+  if (bwd && (r = check_planes(grad, g_pitch, n, es))) return r;
+  if (fwd && n > 0) {
+    if (!workspace || ws_bytes < polsar_wishart_workspace_bytes(dtype, n)) return POLSAR_E_WORKSPACE;
+    if ((uintptr_t)workspace % 8) return POLSAR_E_ALIGN;
+  }
+  if (n > 0) {
+    const Range rs = span(sigma, 9, s_pitch, n, es), rz = span(z, 9, z_pitch, n, es);
+    if (bwd) {
+      const Range rg = span(grad, 9, g_pitch, n, es);
+      if (overlap(rg, rs) || overlap(rg, rz)) return POLSAR_E_ALIAS;
+    }
+    if (fwd && ell) {
+      const Range re = span(ell, 1, n, n, es);
+      if (overlap(re, rs) || overlap(re, rz) || (bwd && overlap(re, span(grad, 9, g_pitch, n, es))))
+        return POLSAR_E_ALIAS;
+    }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (n == 0) {
+    if (fwd) {
+      // an empty sum is zero: reduce zero partials
+      hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, (const double*)workspace, (int64_t)0, loss);
+      if (hipGetLastError() != hipSuccess) return POLSAR_E_HIP;
+    }
+    return POLSAR_OK;
+  }
+  WishartArgs a{sigma, s_pitch, z, z_pitch, n_looks, fwd ? ell : nullptr, (double*)workspace, grad_loss,
+                bwd ? grad : nullptr, g_pitch, counters, n, 0, 0, fwd ? 1 : 0, bwd ? 1 : 0};
+  const bool vec = vec_ok(sigma, s_pitch, es) && vec_ok(z, z_pitch, es) && (!bwd || vec_ok(grad, g_pitch, es)) &&
+                   (!(fwd && ell) || vec_ok(ell, 0, es));
+  const polsar_launch c = get_cfg(1, dtype, 0, 0);
+  hipError_t e = dtype == POLSAR_F32 ? dispatch_wishart<float>(c, vec, a, s) : dispatch_wishart<double>(c, vec, a, s);
+  if (e != hipSuccess) return POLSAR_E_HIP;
+  if (fwd) {
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, (const double*)workspace, a.tiles, loss);
+    if (hipGetLastError() != hipSuccess) return POLSAR_E_HIP;
+  }
+  return POLSAR_OK;
+}
+
+int polsar_autotune_inv_det(int dtype, int method, int precision, int64_t n, const void* z, int64_t z_pitch,
+                            void* inv, int64_t inv_pitch, void* det, int reps, polsar_launch* best,
+                            float* best_ms, void* stream) {
+  InvDetArgs a;
+  bool vec = false;
+  int r = prepare_inv_det(dtype, method, precision, n, z, z_pitch, inv, inv_pitch, det, nullptr, nullptr, a, vec);
+  if (r) return r;
+  if (n == 0 || reps <= 0) return POLSAR_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return POLSAR_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return POLSAR_E_HIP;
+  }
+  const int op = op_code(method, precision);
+  polsar_launch win{0, 0, 0, 0};
+  float win_ms = 1e30f;
+  int rc = POLSAR_OK;
+  for (int block : {64, 128, 256})
+    for (int unroll : {1, 2, 4})
+      for (int gpc : {0, 2, 4, 8})
+        for (int nt : {0, 1}) {
+          polsar_launch c{block, unroll, gpc, nt};
+          InvDetArgs aa = a;
+          if (launch_inv_det(dtype, op, c, vec, aa, s) != hipSuccess) { rc = POLSAR_E_HIP; goto done; }
+          (void)hipEventRecord(e0, s);
+          for (int i = 0; i < reps; ++i) {
+            aa = a;
+            (void)launch_inv_det(dtype, op, c, vec, aa, s);
+          }
+          (void)hipEventRecord(e1, s);
+          if (hipEventSynchronize(e1) != hipSuccess) { rc = POLSAR_E_HIP; goto done; }
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          ms /= reps;
+          if (ms < win_ms) { win_ms = ms; win = c; }
+        }
+  {
+    std::lock_guard<std::mutex> g(g_mu);
+    g_cfg[std::make_tuple(0, dtype, method, precision)] = win;
+  }
+  if (best) *best = win;
+  if (best_ms) *best_ms = win_ms;
+done:
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+int polsar_stream_copy(int dtype, int64_t n, const void* src, int64_t src_pitch, int n_in, void* dst,
+                       int64_t dst_pitch, int n_out, void* stream) {
+  if (dtype != POLSAR_F32 && dtype != POLSAR_F64) return POLSAR_E_ARG;
+  if (n < 0) return POLSAR_E_ARG;
+  const size_t es = esize(dtype);
+  int r = check_planes(src, src_pitch, n, es);
+  if (r) return r;
+  if ((r = check_planes(dst, dst_pitch, n, es))) return r;
+  const bool shape_ok = (n_in == 9 && n_out == 10) || (n_in == 18 && n_out == 9) || (n_in == 1 && n_out == 1);
+  if (!shape_ok) return POLSAR_E_UNSUPPORTED;
+  if (!vec_ok(src, src_pitch, es) || !vec_ok(dst, dst_pitch, es)) return POLSAR_E_ALIGN;
+  if (n > 0 && overlap(span(src, n_in, src_pitch, n, es), span(dst, n_out, dst_pitch, n, es))) return POLSAR_E_ALIAS;
+  if (n == 0) return POLSAR_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const int VW = (int)(16 / es);
+  const int64_t nvec = n / VW;
+  const int64_t grid = std::max<int64_t>(1, (nvec + 255) / 256);
+#define POLSAR_COPY(T, V, NI, NO)                                                                              \
+  hipLaunchKernelGGL((k_copy<T, V, NI, NO>), dim3((unsigned)grid), dim3(256), 0, s, (const T*)src, src_pitch, \
+                     (T*)dst, dst_pitch, nvec, n)
+  if (dtype == POLSAR_F32) {
+    if (n_in == 9) POLSAR_COPY(float, 4, 9, 10);
+    else if (n_in == 18) POLSAR_COPY(float, 4, 18, 9);
+    else POLSAR_COPY(float, 4, 1, 1);
+  } else {
+    if (n_in == 9) POLSAR_COPY(double, 2, 9, 10);
+    else if (n_in == 18) POLSAR_COPY(double, 2, 18, 9);
+    else POLSAR_COPY(double, 2, 1, 1);
+  }
+#undef POLSAR_COPY
+  return hipGetLastError() == hipSuccess ? POLSAR_OK : POLSAR_E_HIP;
+}
+
+}  // extern "C"

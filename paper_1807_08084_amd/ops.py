@@ -1,0 +1,188 @@
+"""torch-facing calls of the C ABI.  Argument marshalling only: every step of
+the computation runs in the HIP kernels of libpolsar.so.
+
+Tensors hold packed planes with the plane index first: shape (9, ...) on the
+GPU, float32 or float64, each plane contiguous (plane pitch = stride(0)).
+Plane order a, d, f, Re b, Im b, Re c, Im c, Re e, Im e (upper triangle).
+Work is enqueued on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib as L
+
+_METHODS = {"adjugate": L.ADJUGATE, "cholesky": L.CHOLESKY}
+_PRECS = {"plain": L.PLAIN, "compensated": L.COMPENSATED, "wide": L.WIDE}
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return L.F32
+    if t.dtype == torch.float64:
+        return L.F64
+    raise TypeError(f"planes must be float32 or float64, got {t.dtype}")
+
+
+def _planes(t: torch.Tensor, name: str) -> tuple[int, int]:
+    """(n, pitch) of a (9, ...) plane tensor; each plane must be contiguous."""
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dim() < 2 or t.shape[0] != 9:
+        raise ValueError(f"{name} must have shape (9, ...), got {tuple(t.shape)}")
+    n = t[0].numel()
+    if not t[0].is_contiguous():
+        raise ValueError(f"{name}: each plane must be contiguous")
+    return n, t.stride(0)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def inv_det(z: torch.Tensor, method: str = "adjugate", precision: str = "compensated", *,
+            inv: torch.Tensor | None = None, det: torch.Tensor | None = None,
+            status: bool | torch.Tensor = False, counters: torch.Tensor | None = None,
+            want_inv: bool = True, want_det: bool = True, stream=None):
+    """Inverse and determinant of every packed matrix of ``z``.
+
+    Returns (inv, det, status) where each is a new tensor (or the one given),
+    or None when not requested.  ``counters``: int64 tensor of 3 on the GPU,
+    added to ([not_pd, rerouted, nonfinite]).
+    """
+    dt = _dtype_code(z)
+    n, zp = _planes(z, "z")
+    shape = z.shape[1:]
+    if inv is None and want_inv:
+        inv = torch.empty_like(z, memory_format=torch.contiguous_format)
+    ip = _planes(inv, "inv")[1] if inv is not None else 0
+    if det is None and want_det:
+        det = torch.empty(shape, dtype=z.dtype, device=z.device)
+    st = None
+    if isinstance(status, torch.Tensor):
+        st = status
+    elif status:
+        st = torch.empty(shape, dtype=torch.uint8, device=z.device)
+    if counters is not None and (counters.dtype != torch.int64 or counters.numel() != 3 or not counters.is_cuda):
+        raise ValueError("counters must be a GPU int64 tensor of 3 elements")
+    rc = L.lib().polsar_inv_det(dt, _METHODS[method], _PRECS[precision], n, _ptr(z), zp,
+                                _ptr(inv), ip, _ptr(det), _ptr(st), _ptr(counters), _stream(stream))
+    L.check(rc, "polsar_inv_det")
+    return inv, det, st
+
+
+def workspace_bytes(dtype: torch.dtype, n: int) -> int:
+    return int(L.lib().polsar_wishart_workspace_bytes(L.F32 if dtype == torch.float32 else L.F64, n))
+
+
+def wishart_loglik(sigma: torch.Tensor, z: torch.Tensor, n_looks: float, *, forward: bool = True,
+                   backward: bool = False, grad_loss: torch.Tensor | None = None, ell: bool = False,
+                   counters: torch.Tensor | None = None, workspace: torch.Tensor | None = None, stream=None):
+    """L = sum N (ln det S + tr(S^-1 Z)) and/or its packed gradient.
+
+    Returns (loss 0-d float64 GPU tensor or None, grad or None, ell or None).
+    """
+    if sigma.dtype != z.dtype:
+        raise TypeError("sigma and z must have the same dtype")
+    dt = _dtype_code(sigma)
+    n, sp = _planes(sigma, "sigma")
+    nz, zp = _planes(z, "z")
+    if nz != n:
+        raise ValueError("sigma and z differ in size")
+    mode = (L.FWD if forward else 0) | (L.BWD if backward else 0)
+    if mode == 0:
+        raise ValueError("nothing to do")
+    loss = torch.empty((), dtype=torch.float64, device=sigma.device) if forward else None
+    grad = torch.empty_like(sigma, memory_format=torch.contiguous_format) if backward else None
+    gp = _planes(grad, "grad")[1] if grad is not None else 0
+    el = torch.empty(sigma.shape[1:], dtype=sigma.dtype, device=sigma.device) if (ell and forward) else None
+    wsb = workspace_bytes(sigma.dtype, n) if forward else 0
+    if forward and (workspace is None or workspace.numel() * workspace.element_size() < wsb):
+        workspace = torch.empty(max(1, (wsb + 7) // 8), dtype=torch.float64, device=sigma.device)
+    if grad_loss is not None:
+        grad_loss = grad_loss.to(dtype=torch.float64).reshape(()).contiguous()
+    ws_size = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    rc = L.lib().polsar_wishart_loglik(dt, mode, n, _ptr(sigma), sp, _ptr(z), zp, float(n_looks),
+                                       _ptr(loss), _ptr(el), _ptr(grad_loss), _ptr(grad), gp,
+                                       _ptr(workspace), ws_size, _ptr(counters), _stream(stream))
+    L.check(rc, "polsar_wishart_loglik")
+    return loss, grad, el
+
+
+class WishartNLL(torch.autograd.Function):
+    """L(S) = sum_px N (ln det S + tr(S^-1 Z)) with the hand-written adjoint.
+
+    forward(sigma, z, n_looks) -> 0-d float64 tensor.  backward recomputes
+    S^-1 from the adjugate (nothing but the inputs is saved) and returns the
+    gradient with respect to the packed real planes of S (off-diagonal
+    components doubled; what finite differences on the planes measure).
+    """
+
+    @staticmethod
+    def forward(ctx, sigma, z, n_looks):
+        loss, _, _ = wishart_loglik(sigma, z, n_looks, forward=True)
+        ctx.save_for_backward(sigma, z)
+        ctx.n_looks = float(n_looks)
+        return loss
+
+    @staticmethod
+    def backward(ctx, g):
+        sigma, z = ctx.saved_tensors
+        _, grad, _ = wishart_loglik(sigma, z, ctx.n_looks, forward=False, backward=True, grad_loss=g)
+        return grad, None, None
+
+
+def wishart_nll(sigma: torch.Tensor, z: torch.Tensor, n_looks: float) -> torch.Tensor:
+    return WishartNLL.apply(sigma, z, n_looks)
+
+
+def stream_copy(src: torch.Tensor, dst: torch.Tensor, n_in: int, n_out: int, n: int, stream=None):
+    """Bandwidth probe: n_in planes of src -> n_out planes of dst."""
+    dt = _dtype_code(src)
+    rc = L.lib().polsar_stream_copy(dt, n, _ptr(src), src.stride(0), n_in, _ptr(dst), dst.stride(0), n_out,
+                                    _stream(stream))
+    L.check(rc, "polsar_stream_copy")
+
+
+def get_launch(op: int, dtype: torch.dtype, method: str = "adjugate", precision: str = "compensated") -> dict:
+    c = L.Launch()
+    d = L.F32 if dtype == torch.float32 else L.F64
+    L.check(L.lib().polsar_get_launch(op, d, _METHODS[method], _PRECS[precision], ctypes.byref(c)),
+            "polsar_get_launch")
+    return c.as_dict()
+
+
+def set_launch(op: int, dtype: torch.dtype, method: str, precision: str, cfg: dict) -> None:
+    c = L.Launch(**cfg)
+    d = L.F32 if dtype == torch.float32 else L.F64
+    L.check(L.lib().polsar_set_launch(op, d, _METHODS[method], _PRECS[precision], ctypes.byref(c)),
+            "polsar_set_launch")
+
+
+def autotune_inv_det(z: torch.Tensor, method: str = "adjugate", precision: str = "compensated",
+                     reps: int = 5, stream=None) -> tuple[dict, float]:
+    """Time every launch configuration on z (scratch outputs), install the best."""
+    dt = _dtype_code(z)
+    n, zp = _planes(z, "z")
+    inv = torch.empty_like(z, memory_format=torch.contiguous_format)
+    det = torch.empty(z.shape[1:], dtype=z.dtype, device=z.device)
+    best = L.Launch()
+    ms = ctypes.c_float(0)
+    rc = L.lib().polsar_autotune_inv_det(dt, _METHODS[method], _PRECS[precision], n, _ptr(z), zp, _ptr(inv),
+                                         inv.stride(0), _ptr(det), reps, ctypes.byref(best), ctypes.byref(ms),
+                                         _stream(stream))
+    L.check(rc, "polsar_autotune_inv_det")
+    return best.as_dict(), float(ms.value)
+
+
+def compute_units() -> int:
+    c = ctypes.c_int(0)
+    L.check(L.lib().polsar_device_compute_units(ctypes.byref(c)), "polsar_device_compute_units")
+    return c.value

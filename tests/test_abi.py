@@ -1,0 +1,109 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad
+arguments before any HIP call (no GPU needed: no compute call is made)."""
+import ctypes
+
+import pytest
+
+from paper_1807_08084_amd import _lib as L
+
+FAKE = 0x10000          # 16-byte aligned stand-in device addresses; never dereferenced
+FAKE2 = 0x20000000
+FAKE3 = 0x40000000
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = L.declared_symbols()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert L.status_string(code) != "unknown status"
+    assert L.status_string(7) == "unknown status"
+
+
+def inv_det(lib, dtype=L.F32, method=L.ADJUGATE, prec=L.COMPENSATED, n=1024, z=FAKE, zp=1024,
+            inv=FAKE2, ip=1024, det=FAKE3, status=None, counters=None):
+    return lib.polsar_inv_det(dtype, method, prec, n, z, zp, inv, ip, det, status, counters, None)
+
+
+def test_inv_det_argument_errors(lib):
+    assert inv_det(lib, n=0) == L.OK                       # empty batch: no launch
+    assert inv_det(lib, z=None) == L.E_ARG
+    assert inv_det(lib, n=-1) == L.E_ARG
+    assert inv_det(lib, zp=1000) == L.E_ARG                # pitch < n
+    assert inv_det(lib, ip=1000) == L.E_ARG
+    assert inv_det(lib, dtype=2) == L.E_ARG
+    assert inv_det(lib, method=2) == L.E_ARG
+    assert inv_det(lib, prec=3) == L.E_ARG
+    assert inv_det(lib, dtype=L.F64, prec=L.WIDE) == L.E_UNSUPPORTED
+    assert inv_det(lib, dtype=L.F64, method=L.CHOLESKY, prec=L.COMPENSATED) == L.E_UNSUPPORTED
+    assert inv_det(lib, z=FAKE + 2) == L.E_ALIGN           # not aligned to 4 bytes
+    assert inv_det(lib, dtype=L.F64, z=FAKE + 4) == L.E_ALIGN
+    assert inv_det(lib, det=FAKE3 + 1) == L.E_ALIGN
+    assert inv_det(lib, inv=None, det=None) == L.E_ARG     # nothing to compute
+    assert inv_det(lib, n=0, inv=FAKE + 64) == L.OK        # n == 0: no overlap to check
+
+
+def test_inv_det_aliasing(lib):
+    assert inv_det(lib, inv=FAKE, ip=1024, n=0) == L.OK
+    assert inv_det(lib, inv=FAKE + 4096) == L.E_ALIAS       # overlaps z, not in place
+    assert inv_det(lib, inv=FAKE, ip=2048, zp=1024) == L.E_ALIAS  # same base, other pitch
+    assert inv_det(lib, det=FAKE + 4 * 9000) == L.E_ALIAS   # det inside z's span
+    assert inv_det(lib, status=FAKE3 + 100) == L.E_ALIAS    # status inside det
+
+
+def test_wishart_argument_errors(lib):
+    def call(dtype=L.F32, mode=L.FWD, n=100, s=FAKE, sp=100, z=FAKE2, zp=100, N=4.0, loss=FAKE3,
+             ell=None, gl=None, grad=None, gp=100, ws=FAKE3 + 4096, wsb=1 << 20):
+        return lib.polsar_wishart_loglik(dtype, mode, n, s, sp, z, zp, N, loss, ell, gl, grad, gp, ws, wsb,
+                                         None, None)
+    assert lib.polsar_wishart_workspace_bytes(L.F32, 100) >= 8
+    assert call(mode=0) == L.E_ARG
+    assert call(N=0.0) == L.E_ARG
+    assert call(s=None) == L.E_ARG
+    assert call(loss=None) == L.E_ARG
+    assert call(ws=None) == L.E_WORKSPACE
+    assert call(wsb=0) == L.E_WORKSPACE
+    assert call(mode=L.BWD, grad=None) == L.E_ARG
+    assert call(mode=L.BWD, grad=FAKE + 64) == L.E_ALIAS
+    assert call(loss=FAKE3 + 4) == L.E_ALIGN
+    assert call(mode=L.BWD, n=0, grad=FAKE3) == L.OK
+
+
+def test_launch_table(lib):
+    c = L.Launch()
+    assert lib.polsar_get_launch(0, L.F32, L.ADJUGATE, L.COMPENSATED, ctypes.byref(c)) == L.OK
+    assert c.block in (64, 128, 256) and c.unroll in (1, 2, 4)
+    bad = L.Launch(block=96, unroll=1, grid_per_cu=0, nontemporal=1)
+    assert lib.polsar_set_launch(0, L.F32, L.ADJUGATE, L.PLAIN, ctypes.byref(bad)) == L.E_ARG
+    bad = L.Launch(block=128, unroll=4, grid_per_cu=0, nontemporal=1)
+    assert lib.polsar_set_launch(1, L.F32, 0, 0, ctypes.byref(bad)) == L.E_ARG   # wishart: unroll <= 2
+    good = L.Launch(block=128, unroll=2, grid_per_cu=4, nontemporal=0)
+    assert lib.polsar_set_launch(0, L.F64, L.CHOLESKY, L.PLAIN, ctypes.byref(good)) == L.OK
+    got = L.Launch()
+    lib.polsar_get_launch(0, L.F64, L.CHOLESKY, L.PLAIN, ctypes.byref(got))
+    assert got.as_dict() == good.as_dict()
+
+
+def test_batch_and_copy_argument_errors(lib):
+    h = ctypes.c_void_p()
+    arr = (L.Image * 1)()
+    assert lib.polsar_batch_create(arr, 1, L.F32, L.ADJUGATE, L.COMPENSATED, 1, None, None, 0, ctypes.byref(h)) == L.E_ARG
+    assert lib.polsar_batch_create(arr, 0, L.F32, L.ADJUGATE, L.COMPENSATED, 1, None, None, 0, ctypes.byref(h)) == L.E_ARG
+    arr[0].n, arr[0].z, arr[0].z_pitch, arr[0].det = 16, FAKE, 16, FAKE2
+    assert lib.polsar_batch_create(arr, 1, L.F32, L.ADJUGATE, L.COMPENSATED, 8, None, None, 0, ctypes.byref(h)) == L.E_ARG
+    assert lib.polsar_batch_create(arr, 1, L.F64, L.ADJUGATE, L.WIDE, 1, None, None, 0, ctypes.byref(h)) == L.E_UNSUPPORTED
+    assert lib.polsar_batch_create(arr, 1, L.F32, L.ADJUGATE, L.PLAIN, 2, None, None, 0, ctypes.byref(h)) == L.E_ARG  # no sigma
+    assert lib.polsar_batch_run(None, None) == L.E_ARG
+    assert lib.polsar_batch_tiles(None) == -1
+    assert lib.polsar_stream_copy(L.F32, 100, FAKE, 100, 5, FAKE2, 100, 10, None) == L.E_UNSUPPORTED
+    assert lib.polsar_stream_copy(L.F32, 100, FAKE, 100, 9, FAKE + 64, 100, 10, None) == L.E_ALIAS
+    assert lib.polsar_stream_copy(L.F32, 0, FAKE, 100, 9, FAKE2, 100, 10, None) == L.OK

@@ -1,0 +1,134 @@
+"""GPU Wishart forward/backward against the oracle, finite differences and
+autograd (S = Z + 0.1 tr(Z)/3 I, Z with N=8 looks, 2x2 regions, lam in
+[1e-2, 1], seed 3)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1807_08084_amd import synth
+from _helpers import flat9, to_np
+
+pytestmark = pytest.mark.gpu
+N = 8.0
+
+
+@pytest.fixture(scope="module")
+def ops():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1807_08084_amd import ops as o
+    o.compute_units()
+    return o
+
+
+@pytest.fixture(scope="module")
+def case():
+    img, sig = synth.workload_wishart(seed=3, side=128)
+    z = img.planes.reshape(9, -1)
+    s = sig.reshape(9, -1)
+    out = {}
+    for key, conv in (("f64", lambda a: a), ("f32", lambda a: a.astype(np.float32).astype(np.float64))):
+        zz, ss = conv(z), conv(s)
+        (eh, el), (gh, gl) = oracle.wishart128(ss, zz, N)
+        out[key] = dict(z=zz, s=ss, eh=eh, el=el, gh=gh, gl=gl, ks=oracle.kappa(ss))
+    return out
+
+
+def _loss_ref(r):
+    return math.fsum(r["eh"]) + math.fsum(r["el"])
+
+
+def _grad_err(g, r):
+    d = (flat9(g) - r["gh"]) - r["gl"]
+    return np.linalg.norm(d, axis=0) / np.linalg.norm(r["gh"], axis=0)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_forward_backward_vs_oracle(ops, case, dtype):
+    key = "f64" if dtype == torch.float64 else "f32"
+    r = case[key]
+    S = torch.from_numpy(r["s"]).to("cuda", dtype)
+    Z = torch.from_numpy(r["z"]).to("cuda", dtype)
+    loss, grad, ell = ops.wishart_loglik(S, Z, N, forward=True, backward=True, ell=True)
+    torch.cuda.synchronize()
+    ref = _loss_ref(r)
+    rel = abs(loss.item() - ref) / abs(ref)
+    e_ell = np.abs(to_np(ell) - r["eh"] - r["el"]) / np.maximum(np.abs(r["eh"]), 1.0)
+    eg = _grad_err(to_np(grad), r)
+    print(f"{key}: loss rel err {rel:.2e}, ell max {e_ell.max():.2e}, grad max {eg.max():.2e}")
+    if dtype == torch.float64:
+        assert rel <= 1e-12 and e_ell.max() <= 1e-12 and eg.max() <= 1e-12
+    else:
+        assert rel <= 1e-5
+        assert np.all(eg <= 2e-6 * r["ks"] ** 2)
+    # separate passes agree with the fused one
+    l2, _, _ = ops.wishart_loglik(S, Z, N, forward=True)
+    _, g2, _ = ops.wishart_loglik(S, Z, N, forward=False, backward=True)
+    assert torch.equal(l2, loss) and torch.equal(g2, grad)
+
+
+def test_gradient_vs_finite_differences(ops, case):
+    """Central differences of the GPU's own FP64 per-pixel terms."""
+    r = case["f64"]
+    m = 64
+    S = torch.from_numpy(np.ascontiguousarray(r["s"][:, :m])).cuda()
+    Z = torch.from_numpy(np.ascontiguousarray(r["z"][:, :m])).cuda()
+    _, g, _ = ops.wishart_loglik(S, Z, N, forward=False, backward=True)
+    g = to_np(g)
+    h = 1e-6 * to_np(S[0] + S[1] + S[2]) / 3.0
+    fd = np.empty_like(g)
+    for k in range(9):
+        sp, sm = S.clone(), S.clone()
+        sp[k] += torch.from_numpy(h).cuda()
+        sm[k] -= torch.from_numpy(h).cuda()
+        _, _, ep = ops.wishart_loglik(sp, Z, N, ell=True)
+        _, _, em = ops.wishart_loglik(sm, Z, N, ell=True)
+        fd[k] = (to_np(ep) - to_np(em)) / (to_np(sp[k]) - to_np(sm[k]))
+    err = np.linalg.norm(fd - g, axis=0) / np.linalg.norm(g, axis=0)
+    assert err.max() <= 1e-5, err.max()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_autograd_function(ops, case, dtype):
+    r = case["f64" if dtype == torch.float64 else "f32"]
+    S = torch.from_numpy(r["s"]).to("cuda", dtype).requires_grad_(True)
+    Z = torch.from_numpy(r["z"]).to("cuda", dtype)
+    loss = ops.wishart_nll(S, Z, N)
+    (3.0 * loss).backward()
+    _, g, _ = ops.wishart_loglik(S.detach(), Z, N, forward=False, backward=True)
+    _, g3, _ = ops.wishart_loglik(S.detach(), Z, N, forward=False, backward=True,
+                                  grad_loss=torch.tensor(3.0, dtype=torch.float64, device="cuda"))
+    assert torch.equal(S.grad, g3)
+    assert torch.allclose(S.grad, 3.0 * g, rtol=1e-6 if dtype == torch.float32 else 1e-14)
+
+
+def test_closed_form_at_sigma_equal_z(ops, case):
+    r = case["f64"]
+    Z = torch.from_numpy(r["z"]).cuda()
+    loss, g, ell = ops.wishart_loglik(Z, Z, N, forward=True, backward=True, ell=True)
+    det = np.linalg.det(oracle.full_from_planes(r["z"])).real
+    assert np.allclose(to_np(ell), N * (np.log(det) + 3.0), rtol=1e-13, atol=1e-12)
+    ginv = np.abs(oracle.ge(r["z"])[0]).max(axis=0)
+    assert np.all(np.abs(to_np(g)).max(axis=0) <= 1e-11 * N * ginv)
+
+
+@pytest.mark.parametrize("n", [1, 3, 5, 1001])
+def test_ragged_and_deterministic(ops, case, n):
+    r = case["f64"]
+    S = torch.from_numpy(np.ascontiguousarray(r["s"][:, :n])).cuda()
+    Z = torch.from_numpy(np.ascontiguousarray(r["z"][:, :n])).cuda()
+    l1, g1, _ = ops.wishart_loglik(S, Z, N, forward=True, backward=True)
+    l2, g2, _ = ops.wishart_loglik(S, Z, N, forward=True, backward=True)
+    assert torch.equal(l1, l2) and torch.equal(g1, g2)
+    ref = math.fsum(r["eh"][:n]) + math.fsum(r["el"][:n])
+    assert abs(l1.item() - ref) <= 1e-12 * abs(ref)
+    assert _grad_err(to_np(g1), {k: (v[:, :n] if k in ("gh", "gl") else v) for k, v in r.items()}).max() <= 1e-12
+
+
+def test_empty_sum_is_zero(ops):
+    S = torch.empty((9, 0), dtype=torch.float64, device="cuda")
+    loss, _, _ = ops.wishart_loglik(S, S.clone(), N, forward=True)
+    assert loss.item() == 0.0
