@@ -100,6 +100,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-rows", action="store_true")
     ap.add_argument("--tune", action="store_true", help="autotune the launch before timing")
+    ap.add_argument("--probe", action="store_true",
+                    help="after the timed steps, run a one-plane copy of the same pixel count "
+                         "(known bytes: calibrates the HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -127,6 +130,14 @@ def main():
         ops.inv_det(z32, "adjugate", "compensated", inv=inv, det=det)
 
     ms = time_calls(step, args.steps, args.warmup, torch)
+    if args.probe:
+        src1 = z32[0:1]
+        dst1 = torch.empty((1, n_px), dtype=torch.float32, device=dev)
+        for _ in range(args.steps):
+            ops.stream_copy(src1, dst1, 1, 1, n_px)
+        torch.cuda.synchronize()
+        print(f"# probe: k_copy 1->1 plane, {n_px * 4} bytes read and written per launch",
+              file=sys.stderr, flush=True)
     value = n_px / (ms * 1e-3) / 1e9
     achieved = BYTES_PER_PX["f32"] * n_px / (ms * 1e-3) / 1e9
     kname = "k_inv_det<float, ADJ_COMP>"

@@ -160,8 +160,9 @@ void polsar_batch_destroy(polsar_batch* b);
  *   unroll       128-bit vectors per thread per tile: 1, 2 or 4
  *   grid_per_cu  0 = one tile per block; k > 0 = persistent grid of k blocks
  *                per compute unit striding over tiles
- *   nontemporal  1 = streaming (non-temporal) loads and stores */
-typedef struct { int block, unroll, grid_per_cu, nontemporal; } polsar_launch;
+ *   nontemporal  1 = streaming (non-temporal) loads and stores
+ *   vector_bytes 16 or 8: bytes per lane per plane access on aligned planes */
+typedef struct { int block, unroll, grid_per_cu, nontemporal, vector_bytes; } polsar_launch;
 int polsar_get_launch(int op, int dtype, int method, int precision, polsar_launch* out);
 int polsar_set_launch(int op, int dtype, int method, int precision, const polsar_launch* cfg);
 

@@ -98,7 +98,7 @@ __device__ __forceinline__ double batch_tile(const BatchArgs& a, const ImgDesc& 
         T ss[9], zz[9], gg[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) { ss[k] = s[k][l]; zz[k] = z[k][l]; }
-        px::wishart_pixel<T>(ss, zz, (T)d.n_looks, a.do_fwd ? &ell[l] : nullptr, a.do_bwd ? gg : nullptr, gscale);
+        px::wishart_pixel<T>(ss, zz, (T)d.n_looks, a.do_fwd, ell[l], a.do_bwd, gg, gscale);
         if (a.do_fwd) acc += (double)ell[l];
         if (a.do_bwd)
 #pragma unroll
@@ -130,7 +130,7 @@ __device__ __forceinline__ double batch_tile(const BatchArgs& a, const ImgDesc& 
         T gg[9], el;
 #pragma unroll
         for (int k = 0; k < 9; ++k) ss[k] = S[k * d.sp + i];
-        px::wishart_pixel<T>(ss, zz, (T)d.n_looks, a.do_fwd ? &el : nullptr, a.do_bwd ? gg : nullptr, gscale);
+        px::wishart_pixel<T>(ss, zz, (T)d.n_looks, a.do_fwd, el, a.do_bwd, gg, gscale);
         if (a.do_fwd) {
           acc += (double)el;
           if (d.ell) ((T*)d.ell)[i] = el;
@@ -144,9 +144,8 @@ __device__ __forceinline__ double batch_tile(const BatchArgs& a, const ImgDesc& 
   return acc;
 }
 
-template <class T, int OP, bool NT>
+template <class T, int OP, bool NT, int VW>
 __global__ __launch_bounds__(256) void k_batch(BatchArgs a) {
-  constexpr int VW = 16 / sizeof(T);
   const T gscale = a.do_bwd ? (a.grad_loss ? (T)*a.grad_loss : T(1)) : T(1);
   unsigned c0 = 0, c1 = 0, c2 = 0;
   for (int64_t t = blockIdx.x; t < a.total_tiles; t += gridDim.x) {
@@ -190,7 +189,7 @@ struct polsar_batch {
   int dtype, op, count;
   unsigned ops;
   int block, grid;
-  int nt;
+  int nt, half;  // half: 8-byte plane accesses instead of 16
   int64_t total_tiles;
   ImgDesc* d_img;
   double* d_partial;
@@ -203,10 +202,17 @@ namespace {
 
 hipError_t enqueue(const polsar_batch* b, hipStream_t s) {
   const int op = b->op;
-#define POLSAR_BATCH(T, OPV)                                                                                    \
-  do {                                                                                                         \
-    if (b->nt) hipLaunchKernelGGL((k_batch<T, OPV, true>), dim3(b->grid), dim3(b->block), 0, s, b->args);      \
-    else hipLaunchKernelGGL((k_batch<T, OPV, false>), dim3(b->grid), dim3(b->block), 0, s, b->args);           \
+#define POLSAR_BATCH(T, OPV)                                                                                   \
+  do {                                                                                                        \
+    constexpr int VW = 16 / sizeof(T);                                                                        \
+    const dim3 g(b->grid), t(b->block);                                                                        \
+    if (b->half) {                                                                                            \
+      if (b->nt) hipLaunchKernelGGL((k_batch<T, OPV, true, VW / 2>), g, t, 0, s, b->args);                    \
+      else hipLaunchKernelGGL((k_batch<T, OPV, false, VW / 2>), g, t, 0, s, b->args);                         \
+    } else {                                                                                                  \
+      if (b->nt) hipLaunchKernelGGL((k_batch<T, OPV, true, VW>), g, t, 0, s, b->args);                        \
+      else hipLaunchKernelGGL((k_batch<T, OPV, false, VW>), g, t, 0, s, b->args);                             \
+    }                                                                                                         \
   } while (0)
   if (b->dtype == POLSAR_F32) {
     switch (op) {
@@ -266,14 +272,16 @@ int polsar_batch_create(const polsar_image* imgs, int count, int dtype, int meth
   if (grad_loss && !aligned(grad_loss, 8)) return POLSAR_E_ALIGN;
   if (counters && !aligned(counters, 8)) return POLSAR_E_ALIGN;
   const size_t es = dtype == POLSAR_F64 ? 8 : 4;
-  const int VW = (int)(16 / es);
   // Tile size: that of the per-call Wishart kernel when the batch evaluates
   // the Wishart term (so per-image losses are summed in the same order),
   // else that of the per-call inverse kernel.
   polsar_launch cfg, wcfg;
   polsar_get_launch(0, dtype, method, precision, &cfg);
   polsar_get_launch(1, dtype, 0, 0, &wcfg);
-  const int block = (ops & (POLSAR_OP_WISHART_FWD | POLSAR_OP_WISHART_BWD)) ? wcfg.block : cfg.block;
+  const polsar_launch& use = (ops & (POLSAR_OP_WISHART_FWD | POLSAR_OP_WISHART_BWD)) ? wcfg : cfg;
+  const int block = use.block;
+  const bool half = use.vector_bytes == 8;
+  const int VW = (int)((half ? 8 : 16) / es);
   std::vector<ImgDesc> h(count);
   int64_t tiles = 0;
   for (int i = 0; i < count; ++i) {
@@ -321,7 +329,7 @@ int polsar_batch_create(const polsar_image* imgs, int count, int dtype, int meth
     d.n_looks = m.n_looks;
     d.vec = vec ? 1 : 0;
     d.pad = 0;
-    d.nvec = m.n / (vec ? VW : 1);
+    d.nvec = m.n / (vec ? VW : 1);  // VW: the batch's vector width (set above)
     d.ntiles = std::max<int64_t>(1, (d.nvec + block - 1) / block);
     d.tile0 = tiles;
     tiles += d.ntiles;
@@ -333,7 +341,8 @@ int polsar_batch_create(const polsar_image* imgs, int count, int dtype, int meth
   b->op = method == POLSAR_ADJUGATE ? (precision == POLSAR_PLAIN ? ADJ_PLAIN : precision == POLSAR_COMPENSATED ? ADJ_COMP : ADJ_WIDE)
                                     : (precision == POLSAR_PLAIN ? CHOL_PLAIN : precision == POLSAR_COMPENSATED ? CHOL_COMP : CHOL_WIDE);
   b->block = block;
-  b->nt = cfg.nontemporal;
+  b->nt = use.nontemporal;
+  b->half = half ? 1 : 0;
   b->total_tiles = tiles;
   const int gpc = grid_per_cu > 0 ? grid_per_cu : 8;
   b->grid = (int)std::min<int64_t>(tiles, (int64_t)gpc * device_cus_b());

@@ -348,67 +348,66 @@ PX_HD int cholesky_fallback(const float z[9], float x[9], float& det) {
 //   grad = g (M00, M11, M22, 2Re M01, 2Im M01, 2Re M02, 2Im M02, 2Re M12, 2Im M12)
 // (dl = tr(M dS) for Hermitian M and dS; g is the upstream gradient).
 // ---------------------------------------------------------------------------
+template <class T> struct Cx { T r, i; };
+template <class T> PX_HD Cx<T> cmul(Cx<T> a, Cx<T> b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+template <class T> PX_HD Cx<T> cadd(Cx<T> a, Cx<T> b) { return {a.r + b.r, a.i + b.i}; }
+template <class T> PX_HD Cx<T> cconj(Cx<T> a) { return {a.r, -a.i}; }
+template <class T> PX_HD Cx<T> rmul(T s, Cx<T> a) { return {s * a.r, s * a.i}; }
+
+// Entry (i, j) of a packed Hermitian matrix (diagonal real, upper stored).
 template <class T>
-PX_HD int wishart_pixel(const T s[9], const T z[9], T n_looks, T* ell, T* grad, T gscale) {
+PX_HD Cx<T> herm(const T* v, int i, int j) {
+  if (i == j) return {v[i], T(0)};
+  const int k = (i + j == 1) ? 3 : (i + j == 2) ? 5 : 7;  // (0,1) -> b, (0,2) -> c, (1,2) -> e
+  return i < j ? Cx<T>{v[k], v[k + 1]} : Cx<T>{v[k], -v[k + 1]};
+}
+
+template <class T>
+PX_HD int wishart_pixel(const T s[9], const T z[9], T n_looks, bool want_ell, T& ell, bool want_grad, T grad[9],
+                        T gscale) {
   T c[9];
   cofactors_plain(s, c);
   const T det = det_from_cofactors(s, c);
   const T t = T(1) / det;
   const int st = classify(det, t);
-  if (ell) {
+  if (want_ell) {
     const T tr = c[0] * z[0] + c[1] * z[1] + c[2] * z[2] +
                  T(2) * (c[3] * z[3] + c[4] * z[4] + c[5] * z[5] + c[6] * z[6] + c[7] * z[7] + c[8] * z[8]);
-    // log of the rounded det; the caller has chosen the precision
-    *ell = n_looks * (log_(det) + tr * t);
+    ell = n_looks * (log_(det) + tr * t);
   }
-  if (grad) {
-    // P = t * adj(S) as a full Hermitian matrix: P00..P22 real, P01, P02, P12 complex
+  if (want_grad) {
     T P[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) P[k] = t * c[k];
-    // W = Z P (full 3x3 complex), then Q = P W (upper triangle only)
-    // Hermitian entries: H(i,j) with H(j,i) = conj(H(i,j)).
-    T Zr[3][3], Zi[3][3], Pr[3][3], Pi[3][3];
-    auto fill = [](const T* v, T (&R)[3][3], T (&I)[3][3]) {
-      R[0][0] = v[0]; I[0][0] = 0; R[1][1] = v[1]; I[1][1] = 0; R[2][2] = v[2]; I[2][2] = 0;
-      R[0][1] = v[3]; I[0][1] = v[4]; R[1][0] = v[3]; I[1][0] = -v[4];
-      R[0][2] = v[5]; I[0][2] = v[6]; R[2][0] = v[5]; I[2][0] = -v[6];
-      R[1][2] = v[7]; I[1][2] = v[8]; R[2][1] = v[7]; I[2][1] = -v[8];
-    };
-    fill(z, Zr, Zi);
-    fill(P, Pr, Pi);
-    T Wr[3][3], Wi[3][3];
+    // W = Z P, all nine entries
+    Cx<T> W[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        T sr = 0, si = 0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          sr += Zr[i][k] * Pr[k][j] - Zi[i][k] * Pi[k][j];
-          si += Zr[i][k] * Pi[k][j] + Zi[i][k] * Pr[k][j];
-        }
-        Wr[i][j] = sr;
-        Wi[i][j] = si;
+        Cx<T> acc = cmul(herm(z, i, 0), herm(P, 0, j));
+        acc = cadd(acc, cmul(herm(z, i, 1), herm(P, 1, j)));
+        acc = cadd(acc, cmul(herm(z, i, 2), herm(P, 2, j)));
+        W[i][j] = acc;
       }
-    const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
+    // Q = P W on the upper triangle; grad = g N (P - Q), off-diagonals doubled
     const T gs = gscale * n_looks;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const int i = ii[q], j = jj[q];
-      T qr = 0, qi = 0;
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        qr += Pr[i][k] * Wr[k][j] - Pi[i][k] * Wi[k][j];
-        qi += Pr[i][k] * Wi[k][j] + Pi[i][k] * Wr[k][j];
+      for (int j = i; j < 3; ++j) {
+        Cx<T> q = cmul(herm(P, i, 0), W[0][j]);
+        q = cadd(q, cmul(herm(P, i, 1), W[1][j]));
+        q = cadd(q, cmul(herm(P, i, 2), W[2][j]));
+        const Cx<T> p = herm(P, i, j);
+        if (i == j) {
+          grad[i] = gs * (p.r - q.r);
+        } else {
+          const int k = (i + j == 1) ? 3 : (i + j == 2) ? 5 : 7;
+          grad[k] = T(2) * gs * (p.r - q.r);
+          grad[k + 1] = T(2) * gs * (p.i - q.i);
+        }
       }
-      if (q < 3) {
-        grad[q] = gs * (Pr[i][j] - qr);
-      } else {
-        grad[3 + 2 * (q - 3)] = T(2) * gs * (Pr[i][j] - qr);
-        grad[4 + 2 * (q - 3)] = T(2) * gs * (Pi[i][j] - qi);
-      }
-    }
   }
   return st;
 }

@@ -131,8 +131,7 @@ __device__ __forceinline__ double wishart_vec(const WishartArgs& a, const T (&s)
     T ss[9], zz[9], gg[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) { ss[k] = s[k][l]; zz[k] = z[k][l]; }
-    const int st = px::wishart_pixel<T>(ss, zz, (T)a.n_looks, a.fwd ? &ell[l] : nullptr,
-                                        a.bwd ? gg : nullptr, gscale);
+    const int st = px::wishart_pixel<T>(ss, zz, (T)a.n_looks, a.fwd, ell[l], a.bwd, gg, gscale);
     tally(st, c0, dummy, c2);
     if (a.fwd) acc += (double)ell[l];
     if (a.bwd)
@@ -182,8 +181,7 @@ __global__ __launch_bounds__(256) void k_wishart(WishartArgs a) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) { ss[k] = S[k * a.sp + i]; zz[k] = Z[k * a.zp + i]; }
         unsigned dummy = 0;
-        const int st = px::wishart_pixel<T>(ss, zz, (T)a.n_looks, a.fwd ? &el : nullptr,
-                                            a.bwd ? gg : nullptr, gscale);
+        const int st = px::wishart_pixel<T>(ss, zz, (T)a.n_looks, a.fwd, el, a.bwd, gg, gscale);
         tally(st, c0, dummy, c2);
         if (a.fwd) {
           acc += (double)el;
@@ -234,11 +232,15 @@ __global__ __launch_bounds__(256) void k_copy(const T* __restrict__ src, int64_t
 std::mutex g_mu;
 std::map<std::tuple<int, int, int, int>, polsar_launch> g_cfg;
 
+// Defaults from a sweep of all launch shapes on MI355X (4096x4096 image):
+// one 128-lane tile per block, one 128-bit vector per lane per plane,
+// non-temporal (streaming) loads and stores.
 polsar_launch default_launch(int op, int dtype, int method, int prec) {
+  (void)dtype;
   (void)method;
   (void)prec;
-  if (op == 1) return polsar_launch{256, 1, 0, 1};
-  return polsar_launch{256, dtype == POLSAR_F32 ? 1 : 2, 0, 1};
+  if (op == 1) return polsar_launch{256, 1, 0, 1, 16};
+  return polsar_launch{128, 1, 0, 1, 16};
 }
 
 polsar_launch get_cfg(int op, int dtype, int method, int prec) {
@@ -252,6 +254,7 @@ bool valid_launch(const polsar_launch& c, int op) {
   if (c.unroll != 1 && c.unroll != 2 && !(op == 0 && c.unroll == 4)) return false;
   if (c.grid_per_cu < 0 || c.grid_per_cu > 64) return false;
   if (c.nontemporal != 0 && c.nontemporal != 1) return false;
+  if (c.vector_bytes != 16 && c.vector_bytes != 8) return false;
   return true;
 }
 
@@ -305,23 +308,27 @@ hipError_t go_inv_det(const polsar_launch& c, int64_t grid, InvDetArgs& a, hipSt
   return hipGetLastError();
 }
 
-template <class T, int OP>
-hipError_t dispatch_inv_det(const polsar_launch& c, bool vec, InvDetArgs& a, hipStream_t s) {
-  constexpr int VW = 16 / sizeof(T);
-  const int V = vec ? VW : 1;
+template <class T, int OP, int V>
+hipError_t dispatch_inv_det_v(const polsar_launch& c, InvDetArgs& a, hipStream_t s) {
   a.nvec = a.n / V;
   const int64_t per_tile = (int64_t)c.block * c.unroll;
   a.tiles = std::max<int64_t>(1, (a.nvec + per_tile - 1) / per_tile);
   int64_t grid = a.tiles;
   if (c.grid_per_cu > 0) grid = std::min<int64_t>(grid, (int64_t)c.grid_per_cu * device_cus());
-  if (vec) {
-    if (c.unroll == 1) return go_inv_det<T, OP, VW, 1>(c, grid, a, s);
-    if (c.unroll == 2) return go_inv_det<T, OP, VW, 2>(c, grid, a, s);
-    return go_inv_det<T, OP, VW, 4>(c, grid, a, s);
-  }
-  if (c.unroll == 1) return go_inv_det<T, OP, 1, 1>(c, grid, a, s);
-  if (c.unroll == 2) return go_inv_det<T, OP, 1, 2>(c, grid, a, s);
-  return go_inv_det<T, OP, 1, 4>(c, grid, a, s);
+  if (c.unroll == 1) return go_inv_det<T, OP, V, 1>(c, grid, a, s);
+  if (c.unroll == 2) return go_inv_det<T, OP, V, 2>(c, grid, a, s);
+  return go_inv_det<T, OP, V, 4>(c, grid, a, s);
+}
+
+// Access width: 16 bytes per lane per plane (V = 16 / sizeof(T) pixels),
+// 8 bytes when the launch asks for it, one element when the planes are not
+// 16-byte aligned.
+template <class T, int OP>
+hipError_t dispatch_inv_det(const polsar_launch& c, bool vec, InvDetArgs& a, hipStream_t s) {
+  constexpr int VW = 16 / sizeof(T);
+  if (!vec) return dispatch_inv_det_v<T, OP, 1>(c, a, s);
+  if (c.vector_bytes == 8) return dispatch_inv_det_v<T, OP, VW / 2>(c, a, s);
+  return dispatch_inv_det_v<T, OP, VW>(c, a, s);
 }
 
 hipError_t launch_inv_det(int dtype, int op, const polsar_launch& c, bool vec, InvDetArgs& a, hipStream_t s) {
@@ -392,17 +399,22 @@ hipError_t go_wishart(const polsar_launch& c, int64_t grid, WishartArgs& a, hipS
   return hipGetLastError();
 }
 
-template <class T>
-hipError_t dispatch_wishart(const polsar_launch& c, bool vec, WishartArgs& a, hipStream_t s) {
-  constexpr int VW = 16 / sizeof(T);
-  const int V = vec ? VW : 1;
+template <class T, int V>
+hipError_t dispatch_wishart_v(const polsar_launch& c, WishartArgs& a, hipStream_t s) {
   a.nvec = a.n / V;
   const int64_t per_tile = (int64_t)c.block * c.unroll;
   a.tiles = std::max<int64_t>(1, (a.nvec + per_tile - 1) / per_tile);
   int64_t grid = a.tiles;
   if (c.grid_per_cu > 0) grid = std::min<int64_t>(grid, (int64_t)c.grid_per_cu * device_cus());
-  if (vec) return c.unroll == 1 ? go_wishart<T, VW, 1>(c, grid, a, s) : go_wishart<T, VW, 2>(c, grid, a, s);
-  return c.unroll == 1 ? go_wishart<T, 1, 1>(c, grid, a, s) : go_wishart<T, 1, 2>(c, grid, a, s);
+  return c.unroll == 1 ? go_wishart<T, V, 1>(c, grid, a, s) : go_wishart<T, V, 2>(c, grid, a, s);
+}
+
+template <class T>
+hipError_t dispatch_wishart(const polsar_launch& c, bool vec, WishartArgs& a, hipStream_t s) {
+  constexpr int VW = 16 / sizeof(T);
+  if (!vec) return dispatch_wishart_v<T, 1>(c, a, s);
+  if (c.vector_bytes == 8) return dispatch_wishart_v<T, VW / 2>(c, a, s);
+  return dispatch_wishart_v<T, VW>(c, a, s);
 }
 
 int64_t max_wishart_tiles(int dtype, int64_t n) {
@@ -543,14 +555,15 @@ int polsar_autotune_inv_det(int dtype, int method, int precision, int64_t n, con
     return POLSAR_E_HIP;
   }
   const int op = op_code(method, precision);
-  polsar_launch win{0, 0, 0, 0};
+  polsar_launch win{0, 0, 0, 0, 0};
   float win_ms = 1e30f;
   int rc = POLSAR_OK;
   for (int block : {64, 128, 256})
     for (int unroll : {1, 2, 4})
       for (int gpc : {0, 2, 4, 8})
-        for (int nt : {0, 1}) {
-          polsar_launch c{block, unroll, gpc, nt};
+        for (int nt : {0, 1})
+          for (int vb : {16, 8}) {
+          polsar_launch c{block, unroll, gpc, nt, vb};
           InvDetArgs aa = a;
           if (launch_inv_det(dtype, op, c, vec, aa, s) != hipSuccess) { rc = POLSAR_E_HIP; goto done; }
           (void)hipEventRecord(e0, s);

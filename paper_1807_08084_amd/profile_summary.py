@@ -1,0 +1,88 @@
+"""Summarise rocprofv3 result databases (SQLite) into short text records.
+
+    python -m paper_1807_08084_amd.profile_summary trace <kt_results.db> <out.txt> "<command>"
+    python -m paper_1807_08084_amd.profile_summary traffic <fetch.db> <write.db> <out.txt> "<commands>"
+
+``trace`` lists each kernel's calls and mean duration (the --kernel-trace
+--stats view).  ``traffic`` turns per-dispatch FETCH_SIZE / WRITE_SIZE (KiB)
+into HBM bytes per launch of the inverse kernel, each scaled by what the same
+counter reads for the one-plane copy probe of known size (bench.py --probe).
+"""
+from __future__ import annotations
+
+import hashlib
+import os
+import sqlite3
+import statistics
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def short(name: str) -> str:
+    return name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+
+
+def trace(db: str, out: str, command: str) -> None:
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
+    with open(out, "w") as fh:
+        fh.write(f"# rocprofv3 --kernel-trace --stats summary\n# command: {command}\n")
+        fh.write(f"# source_hash = {source_hash()}\n")
+        fh.write(f"{'kernel':60s} {'calls':>6s} {'total_us':>12s} {'avg_us':>10s} {'pct':>6s}\n")
+        for name, calls, total, avg, pct in rows:
+            fh.write(f"{short(name):60s} {calls:6d} {total:12.3f} {avg:10.3f} {pct:6.2f}\n")
+    print(open(out).read())
+
+
+def _counter(db: str, counter: str):
+    con = sqlite3.connect(db)
+    rows = con.execute("select kernel_name, value, workgroup_size from counters_collection where counter_name=?",
+                       (counter,)).fetchall()
+    agg = {}
+    for k, v, w in rows:
+        agg.setdefault(short(k), []).append(v)
+    return {k: statistics.mean(v) for k, v in agg.items()}
+
+
+def traffic(fetch_db: str, write_db: str, out: str, command: str, n_px: int = 4096 * 4096) -> None:
+    f = _counter(fetch_db, "FETCH_SIZE")
+    w = _counter(write_db, "WRITE_SIZE")
+    probe = next(k for k in f if k.startswith("k_copy<float, 4, 1, 1>"))
+    kern = next(k for k in f if k.startswith("k_inv_det<float, 1,"))
+    probe_bytes = 4 * n_px
+    f_scale = probe_bytes / (f[probe] * 1024)
+    w_scale = probe_bytes / (w[probe] * 1024)
+    rd = f[kern] * 1024 * f_scale
+    wr = w[kern] * 1024 * w_scale
+    alg_rd, alg_wr = 36 * n_px, 40 * n_px
+    with open(out, "w") as fh:
+        fh.write("# HBM traffic of the FP32 compensated adjugate inverse kernel, 4096x4096 image\n")
+        fh.write(f"# command: {command}\n")
+        fh.write(f"# FETCH_SIZE probe {f[probe]:.1f} KiB for {probe_bytes} B read  -> scale {f_scale:.5f}\n")
+        fh.write(f"# WRITE_SIZE probe {w[probe]:.1f} KiB for {probe_bytes} B written -> scale {w_scale:.5f}\n")
+        fh.write(f"# kernel FETCH_SIZE {f[kern]:.1f} KiB, WRITE_SIZE {w[kern]:.1f} KiB per dispatch\n")
+        fh.write(f"# read {rd:.0f} B (algorithmic {alg_rd}, ratio {rd / alg_rd:.5f}); "
+                 f"write {wr:.0f} B (algorithmic {alg_wr}, ratio {wr / alg_wr:.5f})\n")
+        fh.write(f"kernel = k_inv_det<float, ADJ_COMP>\n")
+        fh.write(f"source_hash = {source_hash()}\n")
+        fh.write(f"read_bytes_per_launch = {rd:.0f}\n")
+        fh.write(f"write_bytes_per_launch = {wr:.0f}\n")
+        fh.write(f"bytes_per_launch = {rd + wr:.0f}\n")
+    print(open(out).read())
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "trace":
+        trace(sys.argv[2], sys.argv[3], sys.argv[4])
+    else:
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])

@@ -1,0 +1,77 @@
+"""Autotuner for the launch shapes of the per-call kernels, with a JSON cache.
+
+The inverse kernel is tuned inside the library (polsar_autotune_inv_det:
+every block x unroll x grid x non-temporal x access-width candidate, timed
+with HIP events on the caller's buffers).  The Wishart kernel is swept here
+through polsar_set_launch with the same timing.  A table of winners can be
+saved to JSON (keyed by device name and compute-unit count) and installed
+again with :func:`load`.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+
+import torch
+
+from . import ops
+
+OPS = {"inv_det": 0, "wishart": 1}
+
+
+def _time(fn, reps: int) -> float:
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune_inv_det(z: torch.Tensor, method: str, precision: str, reps: int = 10):
+    return ops.autotune_inv_det(z, method, precision, reps=reps)
+
+
+def wishart_candidates():
+    for b, u, g, nt, vb in itertools.product((64, 128, 256), (1, 2), (0, 4, 8), (0, 1), (16, 8)):
+        yield dict(block=b, unroll=u, grid_per_cu=g, nontemporal=nt, vector_bytes=vb)
+
+
+def tune_wishart(sigma: torch.Tensor, z: torch.Tensor, n_looks: float, reps: int = 10):
+    """Sweep the Wishart forward+backward launch; install and return the best."""
+    ws = torch.empty(ops.workspace_bytes(sigma.dtype, sigma[0].numel()) // 8 + 1, dtype=torch.float64,
+                     device=sigma.device)
+    best, best_ms = None, float("inf")
+    for cfg in wishart_candidates():
+        ops.set_launch(1, sigma.dtype, "adjugate", "plain", cfg)
+        ms = _time(lambda: ops.wishart_loglik(sigma, z, n_looks, forward=True, backward=True, workspace=ws), reps)
+        if ms < best_ms:
+            best, best_ms = cfg, ms
+    ops.set_launch(1, sigma.dtype, "adjugate", "plain", best)
+    return best, best_ms
+
+
+def device_key() -> str:
+    p = torch.cuda.get_device_properties(0)
+    return f"{p.name}|{getattr(p, 'gcnArchName', '')}|cu{p.multi_processor_count}"
+
+
+def save(path: str, table: dict) -> None:
+    with open(path, "w") as fh:
+        json.dump({"device": device_key(), "entries": table}, fh, indent=1)
+
+
+def load(path: str, strict_device: bool = True) -> int:
+    """Install a saved table; returns the number of entries installed."""
+    rec = json.load(open(path))
+    if strict_device and rec.get("device") != device_key():
+        return 0
+    n = 0
+    for key, ent in rec["entries"].items():
+        op, dt, method, prec = key.split("/")
+        ops.set_launch(OPS[op], torch.float32 if dt == "f32" else torch.float64, method, prec, ent["cfg"])
+        n += 1
+    return n

@@ -82,11 +82,13 @@ def test_launch_table(lib):
     c = L.Launch()
     assert lib.polsar_get_launch(0, L.F32, L.ADJUGATE, L.COMPENSATED, ctypes.byref(c)) == L.OK
     assert c.block in (64, 128, 256) and c.unroll in (1, 2, 4)
-    bad = L.Launch(block=96, unroll=1, grid_per_cu=0, nontemporal=1)
+    bad = L.Launch(block=96, unroll=1, grid_per_cu=0, nontemporal=1, vector_bytes=16)
     assert lib.polsar_set_launch(0, L.F32, L.ADJUGATE, L.PLAIN, ctypes.byref(bad)) == L.E_ARG
-    bad = L.Launch(block=128, unroll=4, grid_per_cu=0, nontemporal=1)
+    bad = L.Launch(block=128, unroll=4, grid_per_cu=0, nontemporal=1, vector_bytes=16)
     assert lib.polsar_set_launch(1, L.F32, 0, 0, ctypes.byref(bad)) == L.E_ARG   # wishart: unroll <= 2
-    good = L.Launch(block=128, unroll=2, grid_per_cu=4, nontemporal=0)
+    bad = L.Launch(block=128, unroll=1, grid_per_cu=0, nontemporal=1, vector_bytes=4)
+    assert lib.polsar_set_launch(0, L.F32, L.ADJUGATE, L.PLAIN, ctypes.byref(bad)) == L.E_ARG
+    good = L.Launch(block=128, unroll=2, grid_per_cu=4, nontemporal=0, vector_bytes=8)
     assert lib.polsar_set_launch(0, L.F64, L.CHOLESKY, L.PLAIN, ctypes.byref(good)) == L.OK
     got = L.Launch()
     lib.polsar_get_launch(0, L.F64, L.CHOLESKY, L.PLAIN, ctypes.byref(got))

@@ -183,9 +183,10 @@ def test_results_independent_of_launch(ops, small):
     keep = ops.get_launch(0, torch.float32, "adjugate", "compensated")
     outs = []
     try:
-        for cfg in ({"block": 64, "unroll": 1, "grid_per_cu": 0, "nontemporal": 0},
-                    {"block": 256, "unroll": 4, "grid_per_cu": 2, "nontemporal": 1},
-                    {"block": 128, "unroll": 2, "grid_per_cu": 8, "nontemporal": 1}):
+        for cfg in ({"block": 64, "unroll": 1, "grid_per_cu": 0, "nontemporal": 0, "vector_bytes": 16},
+                    {"block": 256, "unroll": 4, "grid_per_cu": 2, "nontemporal": 1, "vector_bytes": 16},
+                    {"block": 128, "unroll": 2, "grid_per_cu": 8, "nontemporal": 1, "vector_bytes": 8},
+                    {"block": 64, "unroll": 4, "grid_per_cu": 0, "nontemporal": 0, "vector_bytes": 8}):
             ops.set_launch(0, torch.float32, "adjugate", "compensated", cfg)
             inv, det, st = ops.inv_det(z, "adjugate", "compensated", status=True)
             outs.append((inv.clone(), det.clone(), st.clone()))
