@@ -1,0 +1,55 @@
+"""ctypes access to the host build of the per-pixel compensated arithmetic."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO = os.path.join(HERE, "libpixel_host.so")
+_L = None
+
+
+def lib():
+    global _L
+    if _L is None:
+        src = os.path.join(HERE, "pixel_host.cpp")
+        hdr = os.path.join(HERE, "..", "..", "paper_1807_08084_amd", "csrc", "pixel.hpp")
+        if not os.path.exists(SO) or os.path.getmtime(SO) < max(os.path.getmtime(src), os.path.getmtime(hdr)):
+            tmp = SO + ".tmp"
+            subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fopenmp",
+                                   "-ffp-contract=off", "-o", tmp, src])
+            os.replace(tmp, SO)
+        L = ctypes.CDLL(SO)
+        vp, i64 = ctypes.c_void_p, ctypes.c_int64
+        L.host_adjugate_comp_f32.argtypes = [i64, vp, i64, vp, vp, vp, vp, ctypes.c_int]
+        L.host_adjugate_comp_f32.restype = i64
+        L.host_adjugate_comp_f64.argtypes = [i64, vp, i64, vp, vp, vp, ctypes.c_int]
+        L.host_adjugate_comp_f64.restype = i64
+        _L = L
+    return _L
+
+
+def _threads():
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def adjugate_comp_f32(z):
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.float32).reshape(9, -1))
+    n = z.shape[1]
+    inv, det = np.empty((9, n), np.float32), np.empty(n, np.float32)
+    st, bound = np.empty(n, np.uint8), np.empty(n, np.float32)
+    lib().host_adjugate_comp_f32(n, _p(z), n, _p(inv), _p(det), _p(st), _p(bound), _threads())
+    return inv, det, st, bound
+
+
+def adjugate_comp_f64(z):
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.float64).reshape(9, -1))
+    n = z.shape[1]
+    inv, det, st = np.empty((9, n)), np.empty(n), np.empty(n, np.uint8)
+    lib().host_adjugate_comp_f64(n, _p(z), n, _p(inv), _p(det), _p(st), _threads())
+    return inv, det, st

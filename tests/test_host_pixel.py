@@ -1,0 +1,66 @@
+"""The kernels' compensated per-pixel arithmetic, compiled for the host (no GPU),
+against the __float128 oracle on hard matrices: Haar-rotated, eigenvalues
+(1, l2, 10^-k) with one or two small eigenvalues, kappa up to 1e10.
+
+Checks the FP64 bar (1e-12 up to kappa 1e6), the FP32 bar (2e-6 kappa) after
+rerouting, and that the a-posteriori determinant bound covers the true error
+of every pixel that was not rerouted."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1807_08084_amd import synth
+from _helpers import tol_f32, tol_f64_comp
+
+pixel = pytest.importorskip("host.pixel")
+
+
+def hard(rng, m, kmax=10.0):
+    k = rng.uniform(0.0, kmax, size=m)
+    lam3 = 10.0 ** -k
+    two_small = rng.random(m) < 0.5
+    lam2 = np.where(two_small, lam3 * 10.0 ** rng.uniform(0, 1, m), 10.0 ** -rng.uniform(0, 0.5, m))
+    eig = np.stack([np.ones(m), lam2, lam3], axis=1)
+    U = synth.haar_unitary(rng, m)
+    Z = np.einsum("mij,mj,mkj->mik", U, eig, np.conj(U))
+    return synth.pack(Z)
+
+
+def test_f64_compensated_meets_1e12():
+    rng = np.random.default_rng(31)
+    z = hard(rng, 40000, 8.0)
+    inv, det, st = pixel.adjugate_comp_f64(z)
+    k = oracle.kappa(z)
+    (ih, il), (dh, dl) = oracle.ge128(z)
+    ok = k <= 1e8
+    e_inv = oracle.inv_rel_err(inv, ih, il)
+    e_det = oracle.det_rel_err(det, dh, dl)
+    assert np.all(st[ok] == 0)
+    assert np.all(e_inv[ok] <= tol_f64_comp(k[ok])), e_inv[ok].max()
+    assert np.all(e_det[ok] <= tol_f64_comp(k[ok])), e_det[ok].max()
+    assert np.all(e_inv[k <= 1e6] <= 1e-12) and np.all(e_det[k <= 1e6] <= 1e-12)
+
+
+def test_f32_compensated_reroute_and_bound():
+    rng = np.random.default_rng(32)
+    z32 = hard(rng, 60000, 10.0).astype(np.float32)
+    z = z32.astype(np.float64)
+    inv, det, st, bound = pixel.adjugate_comp_f32(z32)
+    pd = oracle.pd_class(z) == 0
+    k = oracle.kappa(z)
+    (ih, il), (dh, dl) = oracle.ge128(z)
+    e_inv = oracle.inv_rel_err(inv, ih, il)
+    e_det = oracle.det_rel_err(det, dh, dl)
+    assert np.all(e_inv[pd] <= tol_f32(k[pd])) and np.all(e_det[pd] <= tol_f32(k[pd]))
+    # the bound covers the true error wherever the FP32 result was kept
+    kept = st == 0
+    true_err = np.abs((det.astype(np.float64) - dh) - dl)
+    assert kept.sum() > 10000
+    assert np.all(true_err[kept] <= bound[kept].astype(np.float64))
+    # kept pixels meet the 1e-6 relative determinant target
+    assert np.all(e_det[kept] <= 1e-6)
+    # reroutes happen for ill-conditioned matrices only
+    assert np.all(st[k < 100] == 0)
+    assert np.mean(st[(k > 1e6) & pd] == 1) > 0.5
+    # every oracle-PD pixel comes out positive definite (kept or fixed by FP64)
+    assert np.all(st[pd & (k < 1e7)] <= 1)
