@@ -111,7 +111,7 @@ def main():
 
     from paper_1807_08084_amd import synth
     t = time.perf_counter()
-    img = synth.workload_scale()
+    img = synth.workload_scale(with_looks=not args.no_rows)
     z64 = img.planes.reshape(9, -1)
     n_px = z64.shape[1]
     print(f"# generated {n_px} px in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
@@ -119,9 +119,11 @@ def main():
     import torch
     from paper_1807_08084_amd import ops
     dev = torch.device("cuda:0")
-    z32 = torch.from_numpy(z64.astype(np.float32)).to(dev)
-    inv = torch.empty_like(z32)
-    det = torch.empty(n_px, dtype=torch.float32, device=dev)
+    # device layout: planes at the recommended pitch; the 9 inverse planes and
+    # the det plane share one buffer
+    z32 = ops.upload_planes(z64.astype(np.float32), torch.float32, dev)
+    out = ops.empty_planes(10, n_px, torch.float32, dev)
+    inv, det = out[:9], out[9]
     if args.tune:
         cfg, ms = ops.autotune_inv_det(z32, "adjugate", "compensated", reps=5)
         print(f"# tuned {cfg} {ms:.3f} ms", file=sys.stderr, flush=True)
@@ -132,7 +134,7 @@ def main():
     ms = time_calls(step, args.steps, args.warmup, torch)
     if args.probe:
         src1 = z32[0:1]
-        dst1 = torch.empty((1, n_px), dtype=torch.float32, device=dev)
+        dst1 = ops.empty_planes(1, n_px, torch.float32, dev)
         for _ in range(args.steps):
             ops.stream_copy(src1, dst1, 1, 1, n_px)
         torch.cuda.synchronize()
@@ -158,9 +160,9 @@ def main():
         rows = {}
         ksteps = max(10, args.steps // 2)
         for dt, tname in ((torch.float32, "f32"), (torch.float64, "f64")):
-            zt = z32 if dt == torch.float32 else torch.from_numpy(z64).to(dev)
-            it = torch.empty_like(zt)
-            de = torch.empty(n_px, dtype=dt, device=dev)
+            zt = z32 if dt == torch.float32 else ops.upload_planes(z64, dt, dev)
+            o = ops.empty_planes(10, n_px, dt, dev)
+            it, de = o[:9], o[9]
             combos = [("adjugate", "compensated"), ("adjugate", "plain"), ("cholesky", "plain")]
             if dt == torch.float32:
                 combos += [("adjugate", "wide"), ("cholesky", "compensated"), ("cholesky", "wide")]
@@ -170,14 +172,15 @@ def main():
                 gbs = BYTES_PER_PX[tname] * n_px / (t_ms * 1e-3) / 1e9
                 rows[f"{m}_{p}_{tname}"] = {"gpx_s": round(n_px / t_ms / 1e6, 3), "ms": round(t_ms, 4),
                                            "GB_s": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)}
-            dst = torch.empty((10, n_px), dtype=dt, device=dev)
+            dst = ops.empty_planes(10, n_px, dt, dev)
             c_ms = time_calls(lambda: ops.stream_copy(zt, dst, 9, 10, n_px), ksteps, 3, torch)
             cgbs = BYTES_PER_PX[tname] * n_px / (c_ms * 1e-3) / 1e9
             rows[f"copy_9to10_{tname}"] = {"ms": round(c_ms, 4), "GB_s": round(cgbs, 1),
                                           "frac_hbm": round(cgbs / PEAK_HBM_GBS, 4)}
-            del it, de, dst
+            del o, it, de, dst
             # Wishart forward+backward (fused): S = Z + 0.1 tr(Z)/3 I against Z
-            sig = zt.clone()
+            sig = ops.empty_planes(9, n_px, dt, dev)
+            sig.copy_(zt)
             tr = (zt[0] + zt[1] + zt[2]) * (0.1 / 3.0)
             for k in range(3):
                 sig[k] += tr
@@ -188,6 +191,18 @@ def main():
             rows[f"wishart_fwd_bwd_{tname}"] = {"gpx_s": round(n_px / w_ms / 1e6, 3), "ms": round(w_ms, 4),
                                                "GB_s": round(wgbs, 1), "frac_hbm": round(wgbs / PEAK_HBM_GBS, 4)}
             del sig, ws
+        # fused multilook front end (N=4 looks in, inverse + det out), FP32
+        lk = ops.upload_planes(img.looks.reshape(24, -1).astype(np.float32), torch.float32, dev)
+        del img
+        for want_z, tag in ((False, "multilook_fused_f32"), (True, "multilook_fused_with_z_f32")):
+            m_ms = time_calls(lambda: ops.multilook_inv_det(lk, 4, "adjugate", "compensated", want_z=want_z),
+                              ksteps, 3, torch)
+            mb = (24 * 4 + 40 + (36 if want_z else 0)) * n_px
+            rows[tag] = {"gpx_s": round(n_px / m_ms / 1e6, 3), "ms": round(m_ms, 4),
+                         "GB_s": round(mb / (m_ms * 1e-3) / 1e9, 1),
+                         "frac_hbm": round(mb / (m_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                         "bytes_per_px": mb // n_px}
+        del lk
         adj = rows["adjugate_compensated_f32"]["ms"]
         out["rows"] = rows
         out["copy_ceiling_frac"] = round(rows["copy_9to10_f32"]["ms"] / ms, 4)

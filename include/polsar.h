@@ -89,6 +89,23 @@ int polsar_inv_det(int dtype, int method, int precision, int64_t n,
                    void* inv, int64_t inv_pitch, void* det,
                    uint8_t* status, unsigned long long* counters, void* stream);
 
+/* Fused multilook front end + inverse and determinant.  From N single-look
+ * scattering vectors S(l) = (S_HH, S_HV, S_VV) per pixel (Introduction:
+ * reciprocity, the scattering vector, and Eq. ZN read as the outer product)
+ * forms Z = (1/N) sum_l S(l) S(l)^H with FP64 accumulation (for F32 looks
+ * every product is exact), rounds it to the storage type, optionally stores
+ * it, and returns exactly what polsar_inv_det returns for that stored Z.
+ *   looks   in: 6*n_looks planes (pitch looks_pitch); plane 6l + 2i + 0/1 is
+ *           Re/Im of component i (0 HH, 1 HV, 2 VV) of look l
+ *   z       out (nullable): the 9 packed planes of Z (pitch z_pitch)
+ *   inv, det, status, counters as for polsar_inv_det.
+ * Saves the round trip of Z through memory (36 B/px in FP32 written and read
+ * again).  Launch shape: op 2 of polsar_get_launch (unroll must be 1). */
+int polsar_multilook_inv_det(int dtype, int method, int precision, int64_t n, int n_looks,
+                             const void* looks, int64_t looks_pitch, void* z, int64_t z_pitch,
+                             void* inv, int64_t inv_pitch, void* det, uint8_t* status,
+                             unsigned long long* counters, void* stream);
+
 typedef enum { POLSAR_FWD = 1, POLSAR_BWD = 2, POLSAR_FWD_BWD = 3 } polsar_pass;
 
 /* Wishart log-likelihood term, summed over pixels:
@@ -154,8 +171,8 @@ int polsar_batch_run_eager(polsar_batch* b, void* stream);  /* same kernels, no 
 int64_t polsar_batch_tiles(const polsar_batch* b);
 void polsar_batch_destroy(polsar_batch* b);
 
-/* Launch configuration of the per-call kernels (inverse/determinant and
- * Wishart), keyed by op (0 = inv_det, 1 = wishart), dtype, method, precision.
+/* Launch configuration of the per-call kernels, keyed by op (0 = inv_det,
+ * 1 = wishart, 2 = multilook + inv_det), dtype, method, precision.
  *   block        threads per block: 64, 128 or 256
  *   unroll       128-bit vectors per thread per tile: 1, 2 or 4
  *   grid_per_cu  0 = one tile per block; k > 0 = persistent grid of k blocks
@@ -180,6 +197,13 @@ int polsar_autotune_inv_det(int dtype, int method, int precision, int64_t n,
  * the same access pattern as the inverse kernels, for a measured ceiling. */
 int polsar_stream_copy(int dtype, int64_t n, const void* src, int64_t src_pitch, int n_in,
                        void* dst, int64_t dst_pitch, int n_out, void* stream);
+
+/* Plane pitch (in elements) recommended for n-element planes of this dtype:
+ * n rounded up to 64 KiB, plus 32 KiB, so that consecutive planes start 32 KiB
+ * apart modulo 64 KiB instead of at the same offset of every large power of
+ * two (on MI355X, power-of-two plane pitches of hundreds of MB cost up to
+ * 10% of streaming bandwidth).  Any pitch >= n is accepted by every call. */
+int64_t polsar_recommended_pitch(int dtype, int64_t n);
 
 const char* polsar_status_string(int status);
 const char* polsar_version(void);

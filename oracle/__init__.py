@@ -18,6 +18,8 @@ Functions and the passages they follow:
   * pd_class         -- positive-definiteness by the signs of the squared
                         Cholesky pivots in __float128 (Section 3.1's full-rank
                         check, made a sign check).
+  * multilook128      -- Z = (1/N) sum_l S(l) S(l)^H from single-look vectors
+                        (Introduction, Eq. (ZN), the outer product).
   * wishart / wishart128 -- N (ln det S + tr(S^-1 Z)) and its gradient
                         N (S^-1 - S^-1 Z S^-1) in the packed real convention
                         (Introduction: the densities depend on the covariance
@@ -61,8 +63,9 @@ def lib():
         L.oracle_pd_class.argtypes = [i64, dp, i64, u8p, c_int]
         L.oracle_wishart_f64.argtypes = [i64, dp, i64, dp, i64, ctypes.c_double, dp, dp, i64, c_int]
         L.oracle_wishart_f128.argtypes = [i64, dp, i64, dp, i64, ctypes.c_double, dp, dp, dp, dp, i64, c_int]
+        L.oracle_multilook_f128.argtypes = [i64, dp, i64, c_int, dp, dp, i64, dp, c_int]
         for f in ("oracle_ge_f64", "oracle_ge_f128", "oracle_chol_f64", "oracle_chol_f128",
-                  "oracle_pd_class", "oracle_wishart_f64", "oracle_wishart_f128"):
+                  "oracle_pd_class", "oracle_wishart_f64", "oracle_wishart_f128", "oracle_multilook_f128"):
             getattr(L, f).restype = i64
         _lib = L
     return _lib
@@ -158,6 +161,19 @@ def wishart128(sigma, z, n_looks, nthreads=None, grad=True):
                               _p(gh) if grad else None, _p(gl) if grad else None, n,
                               nthreads or threads())
     return (eh, el), ((gh, gl) if grad else None)
+
+
+def multilook128(looks, n_looks, nthreads=None):
+    """Z = (1/N) sum S S^H in __float128 from (6N, ...) look planes.
+    Returns ((z_hi, z_lo) (9, n), mag (9, n)) with mag bounding sum|terms|/N."""
+    lk = np.ascontiguousarray(np.asarray(looks, dtype=np.float64))
+    if lk.shape[0] != 6 * n_looks:
+        raise ValueError("expected 6N look planes")
+    lk = lk.reshape(6 * n_looks, -1)
+    n = lk.shape[1]
+    zh, zl, mag = np.empty((9, n)), np.empty((9, n)), np.empty((9, n))
+    lib().oracle_multilook_f128(n, _p(lk), n, int(n_looks), _p(zh), _p(zl), n, _p(mag), nthreads or threads())
+    return (zh, zl), mag
 
 
 # ------------------------------------------------------------ error metrics

@@ -196,6 +196,39 @@ bool wishart(const Cx<R> S[3][3], const Cx<R> Z[3][3], R n_looks, R& ell, R g[9]
   return true;
 }
 
+// Multilook covariance (Introduction, Eq. (ZN), read as the outer product
+// S S^H): Z = (1/N) sum_l S(l) S(l)^H from N single-look scattering vectors
+// S = (S_HH, S_HV, S_VV).  Look planes: 6l + 2i + 0/1 = Re/Im of S_i of look
+// l.  Also returns, per packed component, (1/N) sum_l |S_i(l)| |S_j(l)|,
+// which bounds the sum of the magnitudes of the terms.
+template <class R>
+void multilook(const double* looks, int64_t lp, int64_t i, int nl, R z[9], double mag[9]) {
+  Cx<R> acc[3][3];
+  R m[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) { acc[r][c] = cx<R>(0, 0); m[r][c] = 0; }
+  for (int l = 0; l < nl; ++l) {
+    Cx<R> S[3];
+    R a[3];
+    for (int k = 0; k < 3; ++k) {
+      S[k] = cx<R>((R)looks[(6 * l + 2 * k) * lp + i], (R)looks[(6 * l + 2 * k + 1) * lp + i]);
+      a[k] = sqrt_(abs2(S[k]));
+    }
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        acc[r][c] = acc[r][c] + S[r] * conj(S[c]);
+        m[r][c] += a[r] * a[c];
+      }
+  }
+  const R inv_n = (R)1 / (R)nl;
+  Cx<R> Z[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) Z[r][c] = scale(acc[r][c], inv_n);
+  pack(Z, z);
+  const int ii[9] = {0, 1, 2, 0, 0, 0, 0, 1, 1}, jj[9] = {0, 1, 2, 1, 1, 2, 2, 2, 2};
+  for (int k = 0; k < 9; ++k) mag[k] = (double)(m[ii[k]][jj[k]] * inv_n);
+}
+
 inline bool finite_input(const double* z, int64_t pitch, int64_t i) {
   for (int k = 0; k < 9; ++k)
     if (!std::isfinite(z[k * pitch + i])) return false;
@@ -341,6 +374,22 @@ int64_t oracle_wishart_f128(int64_t n, const double* s, int64_t sp, const double
       for (int k = 0; k < 9; ++k) split(g[k], grad_hi[k * gp + i], grad_lo[k * gp + i]);
   }
   return bad;
+}
+
+// Multilook in __float128: Z (hi, lo) planes (pitch zp) and magnitudes (pitch zp).
+int64_t oracle_multilook_f128(int64_t n, const double* looks, int64_t lp, int nl, double* z_hi, double* z_lo,
+                              int64_t zp, double* mag, int threads) {
+#pragma omp parallel for num_threads(threads) schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    __float128 z[9];
+    double m[9];
+    multilook(looks, lp, i, nl, z, m);
+    for (int k = 0; k < 9; ++k) {
+      split(z[k], z_hi[k * zp + i], z_lo[k * zp + i]);
+      if (mag) mag[k * zp + i] = m[k];
+    }
+  }
+  return 0;
 }
 
 }  // extern "C"

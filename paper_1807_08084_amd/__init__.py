@@ -7,12 +7,13 @@ ctypes binding.  ``synth`` draws seeded inputs and needs no GPU.
 """
 from . import synth  # noqa: F401
 
-__all__ = ["inv_det", "wishart_loglik", "wishart_nll", "WishartNLL", "BatchPlan", "synth"]
+__all__ = ["inv_det", "multilook_inv_det", "wishart_loglik", "wishart_nll", "WishartNLL", "BatchPlan", "synth"]
 
 
 def __getattr__(name):
     # the binding (and torch) load on first use, so the generator stays light
-    if name in ("inv_det", "wishart_loglik", "wishart_nll", "WishartNLL", "autotune_inv_det",
+    if name in ("inv_det", "multilook_inv_det", "upload_planes", "empty_planes", "recommended_pitch",
+                "wishart_loglik", "wishart_nll", "WishartNLL", "autotune_inv_det",
                 "get_launch", "set_launch", "stream_copy", "compute_units", "workspace_bytes"):
         from . import ops
         return getattr(ops, name)

@@ -58,6 +58,7 @@ def lib():
         L = ctypes.CDLL(SO)
         i, i64, vp, d, sz = ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_double, ctypes.c_size_t
         L.polsar_inv_det.argtypes = [i, i, i, i64, vp, i64, vp, i64, vp, vp, vp, vp]
+        L.polsar_multilook_inv_det.argtypes = [i, i, i, i64, i, vp, i64, vp, i64, vp, i64, vp, vp, vp, vp]
         L.polsar_wishart_loglik.argtypes = [i, i, i64, vp, i64, vp, i64, d, vp, vp, vp, vp, i64, vp, sz, vp, vp]
         L.polsar_wishart_workspace_bytes.argtypes = [i, i64]
         L.polsar_wishart_workspace_bytes.restype = sz
@@ -79,6 +80,8 @@ def lib():
         L.polsar_version.argtypes = []
         L.polsar_version.restype = ctypes.c_char_p
         L.polsar_device_compute_units.argtypes = [ctypes.POINTER(ctypes.c_int)]
+        L.polsar_recommended_pitch.argtypes = [i, i64]
+        L.polsar_recommended_pitch.restype = i64
         _L = L
     return _L
 

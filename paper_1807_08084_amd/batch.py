@@ -6,7 +6,7 @@ import ctypes
 import torch
 
 from . import _lib as L
-from .ops import _METHODS, _PRECS, _dtype_code, _planes, _ptr, _stream
+from .ops import _METHODS, _PRECS, _dtype_code, _planes, _ptr, _stream, empty_planes
 
 
 class BatchPlan:
@@ -42,8 +42,10 @@ class BatchPlan:
             r = arr[i]
             r.n, r.z, r.z_pitch = n, z.data_ptr(), zp
             shape = z.shape[1:]
-            inv = torch.empty_like(z, memory_format=torch.contiguous_format) if inv_det else None
-            det = torch.empty(shape, dtype=dtype, device=dev) if inv_det else None
+            inv = det = None
+            if inv_det:
+                out = empty_planes(10, shape, dtype, dev)  # 9 inverse planes + det, one pitch
+                inv, det = out[:9], out[9]
             st = torch.empty(shape, dtype=torch.uint8, device=dev) if (inv_det and status) else None
             self.inv.append(inv)
             self.det.append(det)
@@ -62,7 +64,7 @@ class BatchPlan:
                     raise ValueError("sigma must match z")
                 r.sigma, r.s_pitch, r.n_looks = s.data_ptr(), sp, float(im["n_looks"])
                 if wishart_bwd:
-                    g = torch.empty_like(s, memory_format=torch.contiguous_format)
+                    g = empty_planes(9, shape, dtype, dev)
                     r.grad, r.g_pitch = g.data_ptr(), g.stride(0)
                 if wishart_fwd:
                     r.loss = self.loss.data_ptr() + 8 * i

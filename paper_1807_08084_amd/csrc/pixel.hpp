@@ -257,6 +257,29 @@ PX_HD int adjugate_comp(const float z[9], float x[9], float& det, float* bound_o
 }
 
 // ---------------------------------------------------------------------------
+// Multilook front end (Introduction, Eq. (ZN), read as the outer product):
+// Z = (1/N) sum_l S(l) S(l)^H for single-look vectors S = (S_HH, S_HV, S_VV).
+// One look's contribution to the nine packed components, accumulated in
+// FP64 (for FP32 looks every product is exact in FP64):
+//   a += |S_HH|^2, d += |S_HV|^2, f += |S_VV|^2,
+//   b += S_HH conj(S_HV), c += S_HH conj(S_VV), e += S_HV conj(S_VV).
+// s = (Re S_HH, Im S_HH, Re S_HV, Im S_HV, Re S_VV, Im S_VV).
+// ---------------------------------------------------------------------------
+template <class T>
+PX_HD void look_accumulate(const T s[6], double acc[9]) {
+  const double hr = s[0], hi = s[1], vr = s[2], vi = s[3], wr = s[4], wi = s[5];
+  acc[0] += hr * hr + hi * hi;
+  acc[1] += vr * vr + vi * vi;
+  acc[2] += wr * wr + wi * wi;
+  acc[3] += hr * vr + hi * vi;
+  acc[4] += hi * vr - hr * vi;
+  acc[5] += hr * wr + hi * wi;
+  acc[6] += hi * wr - hr * wi;
+  acc[7] += vr * wr + vi * wi;
+  acc[8] += vi * wr - vr * wi;
+}
+
+// ---------------------------------------------------------------------------
 // Cholesky comparison form (Section 2.2 and Alg. 1): A = L L^H,
 //   l00 = sqrt(a), v0 = 1/l00, l10 = conj(b) v0, l20 = conj(c) v0,
 //   l11 = sqrt(d - |l10|^2), v1 = 1/l11,

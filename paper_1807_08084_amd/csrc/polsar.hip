@@ -103,6 +103,85 @@ __global__ __launch_bounds__(256) void k_inv_det(InvDetArgs a) {
   if (a.counters) flush_counters(a.counters, c0, c1, c2);
 }
 
+// ------------------------------------------------------------------ multilook
+struct MultilookArgs {
+  const void* looks;
+  int64_t lp;
+  int n_looks;
+  void* z;  // optional output of the multilook covariance
+  int64_t zp;
+  InvDetArgs o;  // outputs (o.z unused), n, nvec, tiles
+};
+
+// Fused multilook front end + inverse/determinant: per lane V pixels, the N
+// looks are streamed (6 planes each) into FP64 accumulators, Z is rounded to
+// the storage type, optionally stored, and inverted exactly as k_inv_det
+// inverts a stored Z.
+template <class T, int OP, int V, bool NT>
+__global__ __launch_bounds__(256) void k_multilook(MultilookArgs a) {
+  const T* __restrict__ S = (const T*)a.looks;
+  const int B = blockDim.x;
+  unsigned c0 = 0, c1 = 0, c2 = 0;
+  const double inv_n_den = (double)a.n_looks;
+  for (int64_t tile = blockIdx.x; tile < a.o.tiles; tile += gridDim.x) {
+    const int64_t v = tile * (int64_t)B + threadIdx.x;
+    if (v < a.o.nvec) {
+      double acc[V][9];
+#pragma unroll
+      for (int l = 0; l < V; ++l)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[l][k] = 0.0;
+#pragma unroll 2
+      for (int look = 0; look < a.n_looks; ++look) {
+        T in[6][V];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) load_v<T, V, NT>(S + (int64_t)(6 * look + j) * a.lp + v * V, in[j]);
+#pragma unroll
+        for (int l = 0; l < V; ++l) {
+          const T s6[6] = {in[0][l], in[1][l], in[2][l], in[3][l], in[4][l], in[5][l]};
+          px::look_accumulate(s6, acc[l]);
+        }
+      }
+      T zz[9][V];
+#pragma unroll
+      for (int l = 0; l < V; ++l)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) zz[k][l] = (T)(acc[l][k] / inv_n_den);
+      if (a.z) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) store_v<T, V, NT>((T*)a.z + k * a.zp + v * V, zz[k]);
+      }
+      inv_det_vec<T, OP, V, NT>(a.o, zz, v, c0, c1, c2);
+    }
+    if (V > 1 && tile == a.o.tiles - 1) {
+      const int64_t i = a.o.nvec * V + threadIdx.x;
+      if (i < a.o.n) {
+        double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int look = 0; look < a.n_looks; ++look) {
+          T s6[6];
+#pragma unroll
+          for (int j = 0; j < 6; ++j) s6[j] = S[(int64_t)(6 * look + j) * a.lp + i];
+          px::look_accumulate(s6, acc);
+        }
+        T zz[9], xx[9], dt;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) zz[k] = (T)(acc[k] / inv_n_den);
+        if (a.z)
+#pragma unroll
+          for (int k = 0; k < 9; ++k) ((T*)a.z)[k * a.zp + i] = zz[k];
+        const int st = run_pixel<T, OP>(zz, xx, dt);
+        tally(st, c0, c1, c2);
+        if (a.o.inv)
+#pragma unroll
+          for (int k = 0; k < 9; ++k) ((T*)a.o.inv)[k * a.o.ip + i] = xx[k];
+        if (a.o.det) ((T*)a.o.det)[i] = dt;
+        if (a.o.status) a.o.status[i] = (uint8_t)st;
+      }
+    }
+  }
+  if (a.o.counters) flush_counters(a.o.counters, c0, c1, c2);
+}
+
 // ------------------------------------------------------------------ Wishart
 struct WishartArgs {
   const void* s;
@@ -240,6 +319,7 @@ polsar_launch default_launch(int op, int dtype, int method, int prec) {
   (void)method;
   (void)prec;
   if (op == 1) return polsar_launch{256, 1, 0, 1, 16};
+  if (op == 2) return polsar_launch{128, 1, 0, 1, 16};
   return polsar_launch{128, 1, 0, 1, 16};
 }
 
@@ -252,6 +332,7 @@ polsar_launch get_cfg(int op, int dtype, int method, int prec) {
 bool valid_launch(const polsar_launch& c, int op) {
   if (c.block != 64 && c.block != 128 && c.block != 256) return false;
   if (c.unroll != 1 && c.unroll != 2 && !(op == 0 && c.unroll == 4)) return false;
+  if (op == 2 && c.unroll != 1) return false;
   if (c.grid_per_cu < 0 || c.grid_per_cu > 64) return false;
   if (c.nontemporal != 0 && c.nontemporal != 1) return false;
   if (c.vector_bytes != 16 && c.vector_bytes != 8) return false;
@@ -350,15 +431,22 @@ hipError_t launch_inv_det(int dtype, int op, const polsar_launch& c, bool vec, I
 }
 
 // Validates polsar_inv_det arguments; fills `a` and `vec` on success.
-int prepare_inv_det(int dtype, int method, int prec, int64_t n, const void* z, int64_t zp, void* inv,
-                    int64_t ip, void* det, uint8_t* status, unsigned long long* counters, InvDetArgs& a,
-                    bool& vec) {
+// Valid (dtype, method, precision) combination?
+int check_mode(int dtype, int method, int prec) {
   if (dtype != POLSAR_F32 && dtype != POLSAR_F64) return POLSAR_E_ARG;
   if (method != POLSAR_ADJUGATE && method != POLSAR_CHOLESKY) return POLSAR_E_ARG;
   if (prec != POLSAR_PLAIN && prec != POLSAR_COMPENSATED && prec != POLSAR_WIDE) return POLSAR_E_ARG;
-  if (n < 0) return POLSAR_E_ARG;
   if (dtype == POLSAR_F64 && prec == POLSAR_WIDE) return POLSAR_E_UNSUPPORTED;
   if (dtype == POLSAR_F64 && method == POLSAR_CHOLESKY && prec != POLSAR_PLAIN) return POLSAR_E_UNSUPPORTED;
+  return POLSAR_OK;
+}
+
+int prepare_inv_det(int dtype, int method, int prec, int64_t n, const void* z, int64_t zp, void* inv,
+                    int64_t ip, void* det, uint8_t* status, unsigned long long* counters, InvDetArgs& a,
+                    bool& vec) {
+  int r0 = check_mode(dtype, method, prec);
+  if (r0) return r0;
+  if (n < 0) return POLSAR_E_ARG;
   const size_t es = esize(dtype);
   int r = check_planes(z, zp, n, es);
   if (r) return r;
@@ -387,6 +475,46 @@ int prepare_inv_det(int dtype, int method, int prec, int64_t n, const void* z, i
   vec = vec_ok(z, zp, es) && vec_ok(inv, ip, es) && vec_ok(det, 0, es) &&
         (status == nullptr || ((uintptr_t)status % VW) == 0);
   return POLSAR_OK;
+}
+
+// ---- multilook launch
+template <class T, int OP, int V>
+hipError_t dispatch_multilook_v(const polsar_launch& c, MultilookArgs& a, hipStream_t s) {
+  a.o.nvec = a.o.n / V;
+  a.o.tiles = std::max<int64_t>(1, (a.o.nvec + c.block - 1) / c.block);
+  int64_t grid = a.o.tiles;
+  if (c.grid_per_cu > 0) grid = std::min<int64_t>(grid, (int64_t)c.grid_per_cu * device_cus());
+  if (c.nontemporal)
+    hipLaunchKernelGGL((k_multilook<T, OP, V, true>), dim3((unsigned)grid), dim3(c.block), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_multilook<T, OP, V, false>), dim3((unsigned)grid), dim3(c.block), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class T, int OP>
+hipError_t dispatch_multilook(const polsar_launch& c, bool vec, MultilookArgs& a, hipStream_t s) {
+  constexpr int VW = 16 / sizeof(T);
+  if (!vec) return dispatch_multilook_v<T, OP, 1>(c, a, s);
+  if (c.vector_bytes == 8) return dispatch_multilook_v<T, OP, VW / 2>(c, a, s);
+  return dispatch_multilook_v<T, OP, VW>(c, a, s);
+}
+
+hipError_t launch_multilook(int dtype, int op, const polsar_launch& c, bool vec, MultilookArgs& a, hipStream_t s) {
+  if (dtype == POLSAR_F32) {
+    switch (op) {
+      case ADJ_PLAIN: return dispatch_multilook<float, ADJ_PLAIN>(c, vec, a, s);
+      case ADJ_COMP: return dispatch_multilook<float, ADJ_COMP>(c, vec, a, s);
+      case ADJ_WIDE: return dispatch_multilook<float, ADJ_WIDE>(c, vec, a, s);
+      case CHOL_PLAIN: return dispatch_multilook<float, CHOL_PLAIN>(c, vec, a, s);
+      case CHOL_COMP: return dispatch_multilook<float, CHOL_COMP>(c, vec, a, s);
+      default: return dispatch_multilook<float, CHOL_WIDE>(c, vec, a, s);
+    }
+  }
+  switch (op) {
+    case ADJ_PLAIN: return dispatch_multilook<double, ADJ_PLAIN>(c, vec, a, s);
+    case ADJ_COMP: return dispatch_multilook<double, ADJ_COMP>(c, vec, a, s);
+    default: return dispatch_multilook<double, CHOL_PLAIN>(c, vec, a, s);
+  }
 }
 
 // ---- Wishart launch
@@ -432,6 +560,13 @@ extern "C" {
 
 const char* polsar_version(void) { return "polsar-mi355x 0.1 (gfx950)"; }
 
+int64_t polsar_recommended_pitch(int dtype, int64_t n) {
+  if ((dtype != POLSAR_F32 && dtype != POLSAR_F64) || n < 0) return -1;
+  const int64_t es = (int64_t)esize(dtype);
+  const int64_t blk = (64 << 10) / es, half = (32 << 10) / es;
+  return (n + blk - 1) / blk * blk + half;
+}
+
 const char* polsar_status_string(int status) {
   switch (status) {
     case POLSAR_OK: return "ok";
@@ -452,13 +587,13 @@ int polsar_device_compute_units(int* cus) {
 }
 
 int polsar_get_launch(int op, int dtype, int method, int precision, polsar_launch* out) {
-  if (!out || (op != 0 && op != 1)) return POLSAR_E_ARG;
+  if (!out || op < 0 || op > 2) return POLSAR_E_ARG;
   *out = get_cfg(op, dtype, method, precision);
   return POLSAR_OK;
 }
 
 int polsar_set_launch(int op, int dtype, int method, int precision, const polsar_launch* cfg) {
-  if (!cfg || (op != 0 && op != 1) || !valid_launch(*cfg, op)) return POLSAR_E_ARG;
+  if (!cfg || op < 0 || op > 2 || !valid_launch(*cfg, op)) return POLSAR_E_ARG;
   std::lock_guard<std::mutex> g(g_mu);
   g_cfg[std::make_tuple(op, dtype, method, precision)] = *cfg;
   return POLSAR_OK;
@@ -473,6 +608,40 @@ int polsar_inv_det(int dtype, int method, int precision, int64_t n, const void* 
   if (n == 0) return POLSAR_OK;
   const polsar_launch c = get_cfg(0, dtype, method, precision);
   if (launch_inv_det(dtype, op_code(method, precision), c, vec, a, (hipStream_t)stream) != hipSuccess)
+    return POLSAR_E_HIP;
+  return POLSAR_OK;
+}
+
+int polsar_multilook_inv_det(int dtype, int method, int precision, int64_t n, int n_looks, const void* looks,
+                             int64_t looks_pitch, void* z, int64_t z_pitch, void* inv, int64_t inv_pitch,
+                             void* det, uint8_t* status, unsigned long long* counters, void* stream) {
+  int r = check_mode(dtype, method, precision);
+  if (r) return r;
+  if (n < 0 || n_looks < 1 || n_looks > 4096) return POLSAR_E_ARG;
+  const size_t es = esize(dtype);
+  if ((r = check_planes(looks, looks_pitch, n, es))) return r;
+  if (z && (r = check_planes(z, z_pitch, n, es))) return r;
+  if (inv && (r = check_planes(inv, inv_pitch, n, es))) return r;
+  if (det && ((uintptr_t)det % es)) return POLSAR_E_ALIGN;
+  if (counters && ((uintptr_t)counters % 8)) return POLSAR_E_ALIGN;
+  if (!z && !inv && !det && !status && !counters) return POLSAR_E_ARG;
+  if (n > 0) {
+    const Range rl = span(looks, 6 * n_looks, looks_pitch, n, es);
+    const Range rz = z ? span(z, 9, z_pitch, n, es) : Range{0, 0};
+    const Range ri = inv ? span(inv, 9, inv_pitch, n, es) : Range{0, 0};
+    const Range rd = det ? span(det, 1, n, n, es) : Range{0, 0};
+    const Range rs = status ? span(status, 1, n, n, 1) : Range{0, 0};
+    const Range all[5] = {rl, rz, ri, rd, rs};
+    for (int p = 0; p < 5; ++p)
+      for (int q = p + 1; q < 5; ++q)
+        if (all[p].hi > all[p].lo && all[q].hi > all[q].lo && overlap(all[p], all[q])) return POLSAR_E_ALIAS;
+  }
+  if (n == 0) return POLSAR_OK;
+  MultilookArgs a{looks, looks_pitch, n_looks, z, z_pitch, InvDetArgs{nullptr, 0, inv, inv_pitch, det, status, counters, n, 0, 0}};
+  const bool vec = vec_ok(looks, looks_pitch, es) && vec_ok(z, z_pitch, es) && vec_ok(inv, inv_pitch, es) && vec_ok(det, 0, es) &&
+        (status == nullptr || ((uintptr_t)status % (16 / es)) == 0);
+  const polsar_launch c = get_cfg(2, dtype, method, precision);
+  if (launch_multilook(dtype, op_code(method, precision), c, vec, a, (hipStream_t)stream) != hipSuccess)
     return POLSAR_E_HIP;
   return POLSAR_OK;
 }

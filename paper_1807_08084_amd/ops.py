@@ -47,6 +47,29 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def recommended_pitch(dtype: torch.dtype, n: int) -> int:
+    return int(L.lib().polsar_recommended_pitch(L.F32 if dtype == torch.float32 else L.F64, int(n)))
+
+
+def empty_planes(k: int, shape, dtype: torch.dtype, device="cuda") -> torch.Tensor:
+    """Uninitialised (k, *shape) planes laid out with the recommended pitch
+    (a view into a (k, pitch) buffer; each plane contiguous)."""
+    shape = tuple(shape) if isinstance(shape, (tuple, list, torch.Size)) else (int(shape),)
+    n = 1
+    for s in shape:
+        n *= s
+    buf = torch.empty((k, recommended_pitch(dtype, n)), dtype=dtype, device=device)
+    return buf[:, :n].view((k,) + shape) if len(shape) > 1 else buf[:, :n]
+
+
+def upload_planes(planes, dtype: torch.dtype, device="cuda") -> torch.Tensor:
+    """Copy host planes (9, ...) into device planes with the recommended pitch."""
+    t = torch.as_tensor(planes)
+    out = empty_planes(t.shape[0], t.shape[1:], dtype, device)
+    out.copy_(t.to(dtype))
+    return out
+
+
 def inv_det(z: torch.Tensor, method: str = "adjugate", precision: str = "compensated", *,
             inv: torch.Tensor | None = None, det: torch.Tensor | None = None,
             status: bool | torch.Tensor = False, counters: torch.Tensor | None = None,
@@ -60,8 +83,11 @@ def inv_det(z: torch.Tensor, method: str = "adjugate", precision: str = "compens
     dt = _dtype_code(z)
     n, zp = _planes(z, "z")
     shape = z.shape[1:]
+    if inv is None and det is None and want_inv and want_det:
+        out = empty_planes(10, shape, z.dtype, z.device)  # 9 inverse planes + det, one pitch
+        inv, det = out[:9], out[9]
     if inv is None and want_inv:
-        inv = torch.empty_like(z, memory_format=torch.contiguous_format)
+        inv = empty_planes(9, shape, z.dtype, z.device)
     ip = _planes(inv, "inv")[1] if inv is not None else 0
     if det is None and want_det:
         det = torch.empty(shape, dtype=z.dtype, device=z.device)
@@ -76,6 +102,30 @@ def inv_det(z: torch.Tensor, method: str = "adjugate", precision: str = "compens
                                 _ptr(inv), ip, _ptr(det), _ptr(st), _ptr(counters), _stream(stream))
     L.check(rc, "polsar_inv_det")
     return inv, det, st
+
+
+def multilook_inv_det(looks: torch.Tensor, n_looks: int, method: str = "adjugate",
+                      precision: str = "compensated", *, want_z: bool = False, status: bool = False,
+                      counters: torch.Tensor | None = None, stream=None):
+    """Fused multilook + inverse/determinant from (6N, ...) look planes.
+
+    Returns (z or None, inv, det, status or None)."""
+    dt = _dtype_code(looks)
+    if looks.dim() < 2 or looks.shape[0] != 6 * n_looks:
+        raise ValueError(f"looks must have shape (6N, ...) with N={n_looks}")
+    if not looks.is_cuda or not looks[0].is_contiguous():
+        raise ValueError("looks must be GPU planes, each contiguous")
+    shape = looks.shape[1:]
+    n, lp = looks[0].numel(), looks.stride(0)
+    out = empty_planes(10, shape, looks.dtype, looks.device)
+    inv, det = out[:9], out[9]
+    z = empty_planes(9, shape, looks.dtype, looks.device) if want_z else None
+    st = torch.empty(shape, dtype=torch.uint8, device=looks.device) if status else None
+    rc = L.lib().polsar_multilook_inv_det(dt, _METHODS[method], _PRECS[precision], n, int(n_looks), _ptr(looks),
+                                          lp, _ptr(z), z.stride(0) if z is not None else 0, _ptr(inv),
+                                          inv.stride(0), _ptr(det), _ptr(st), _ptr(counters), _stream(stream))
+    L.check(rc, "polsar_multilook_inv_det")
+    return z, inv, det, st
 
 
 def workspace_bytes(dtype: torch.dtype, n: int) -> int:
@@ -100,7 +150,7 @@ def wishart_loglik(sigma: torch.Tensor, z: torch.Tensor, n_looks: float, *, forw
     if mode == 0:
         raise ValueError("nothing to do")
     loss = torch.empty((), dtype=torch.float64, device=sigma.device) if forward else None
-    grad = torch.empty_like(sigma, memory_format=torch.contiguous_format) if backward else None
+    grad = empty_planes(9, sigma.shape[1:], sigma.dtype, sigma.device) if backward else None
     gp = _planes(grad, "grad")[1] if grad is not None else 0
     el = torch.empty(sigma.shape[1:], dtype=sigma.dtype, device=sigma.device) if (ell and forward) else None
     wsb = workspace_bytes(sigma.dtype, n) if forward else 0

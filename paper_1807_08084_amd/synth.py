@@ -88,15 +88,22 @@ def unpack(planes: np.ndarray) -> np.ndarray:
     return z
 
 
-def _multilook(rng: np.random.Generator, root: np.ndarray, n_looks: int) -> np.ndarray:
+def _multilook(rng: np.random.Generator, root: np.ndarray, n_looks: int, looks_out=None) -> np.ndarray:
     """Packed Z = (1/N) sum_l S S^H with S = root w, w ~ CN(0, I); root (m, 3, 3).
 
     Returns (9, m) planes; the diagonal is summed as |S_i|^2, exactly real.
+    If ``looks_out`` (6N, m) is given, the looks are written there: plane
+    6l + 2i + 0/1 = Re/Im of component i (HH, HV, VV) of look l.
     """
     m = root.shape[0]
     w = (rng.standard_normal((m, n_looks, 3)) + 1j * rng.standard_normal((m, n_looks, 3))) / math.sqrt(2.0)
     s = [root[:, None, i, 0] * w[:, :, 0] + root[:, None, i, 1] * w[:, :, 1]
          + root[:, None, i, 2] * w[:, :, 2] for i in range(3)]
+    if looks_out is not None:
+        for ll in range(n_looks):
+            for i in range(3):
+                looks_out[6 * ll + 2 * i] = s[i][:, ll].real
+                looks_out[6 * ll + 2 * i + 1] = s[i][:, ll].imag
     out = np.empty((9, m), dtype=np.float64)
     for k in range(3):
         out[k] = (s[k].real ** 2 + s[k].imag ** 2).sum(axis=1) / n_looks
@@ -118,10 +125,12 @@ class Image:
     n_looks: int
     sigma_regions: np.ndarray   # (R, 3, 3) complex, the regional covariances
     region_of: np.ndarray | None = None  # (H, W) int region index (None if per-pixel)
+    looks: np.ndarray | None = None      # (6N, H, W) float64 single-look vectors, if requested
 
 
 def make_image(H: int, W: int, n_looks: int, regions=(2, 2), lam_range=(1e-2, 1.0),
-               seed=0, per_pixel: bool = False, rows: tuple[int, int] | None = None) -> Image:
+               seed=0, per_pixel: bool = False, rows: tuple[int, int] | None = None,
+               with_looks: bool = False) -> Image:
     """Draw one synthetic multilook image; see the module docstring.
 
     ``seed`` is an int or a numpy SeedSequence.  ``rows=(y0, y1)`` draws only
@@ -143,6 +152,7 @@ def make_image(H: int, W: int, n_looks: int, regions=(2, 2), lam_range=(1e-2, 1.
     nchunks = (n + CHUNK - 1) // CHUNK
     children = ss_pix.spawn(nchunks)
     out = np.empty((9, p1 - p0), dtype=np.float64)
+    looks = np.empty((6 * n_looks, p1 - p0), dtype=np.float64) if with_looks else None
 
     def chunk(k: int) -> None:
         c0, c1 = k * CHUNK, min(n, (k + 1) * CHUNK)
@@ -156,9 +166,12 @@ def make_image(H: int, W: int, n_looks: int, regions=(2, 2), lam_range=(1e-2, 1.
             idx = np.arange(c0, c1)
             reg = (idx // W * Ry // H) * Rx + (idx % W * Rx // W)
             root = root_r[reg]
-        z = _multilook(rng, root, n_looks)
+        lk = np.empty((6 * n_looks, c1 - c0)) if with_looks else None
+        z = _multilook(rng, root, n_looks, lk)
         s0, s1 = max(c0, p0), min(c1, p1)
         out[:, s0 - p0:s1 - p0] = z[:, s0 - c0:s1 - c0]
+        if with_looks:
+            looks[:, s0 - p0:s1 - p0] = lk[:, s0 - c0:s1 - c0]
 
     ks = range(p0 // CHUNK, (p1 + CHUNK - 1) // CHUNK) if p1 > p0 else range(0)
     if len(ks) > 1:
@@ -172,7 +185,9 @@ def make_image(H: int, W: int, n_looks: int, regions=(2, 2), lam_range=(1e-2, 1.
     if not per_pixel:
         yy, xx = np.meshgrid(np.arange(y0, y1), np.arange(W), indexing="ij")
         region_of = (yy * Ry // H) * Rx + (xx * Rx // W)
-    return Image(out.reshape(9, y1 - y0, W), n_looks, sig, region_of)
+    if with_looks:
+        looks = looks.reshape(6 * n_looks, y1 - y0, W)
+    return Image(out.reshape(9, y1 - y0, W), n_looks, sig, region_of, looks)
 
 
 def wishart_sigma0(z_planes: np.ndarray, ridge: float = 0.1) -> np.ndarray:
@@ -192,9 +207,9 @@ def workload_small(seed=0):
     return make_image(256, 256, 4, (2, 2), (1e-2, 1.0), seed)
 
 
-def workload_scale(seed=1, rows=None):
+def workload_scale(seed=1, rows=None, with_looks=False):
     """4096x4096, N=4, 4x4 regions, lam in [1e-3, 1]."""
-    return make_image(4096, 4096, 4, (4, 4), (1e-3, 1.0), seed, rows=rows)
+    return make_image(4096, 4096, 4, (4, 4), (1e-3, 1.0), seed, rows=rows, with_looks=with_looks)
 
 
 def workload_precision(seed=2, side=8192, rows=None):

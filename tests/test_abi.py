@@ -23,6 +23,17 @@ def test_exports_every_declared_symbol(lib):
         assert hasattr(lib, name), name
 
 
+def test_recommended_pitch(lib):
+    assert lib.polsar_recommended_pitch(L.F32, 1 << 24) == (1 << 24) + 8192
+    assert lib.polsar_recommended_pitch(L.F64, 1 << 24) == (1 << 24) + 4096
+    assert lib.polsar_recommended_pitch(L.F32, 1) == 16384 + 8192
+    assert lib.polsar_recommended_pitch(L.F32, 0) == 8192
+    assert lib.polsar_recommended_pitch(2, 10) == -1 and lib.polsar_recommended_pitch(L.F32, -1) == -1
+    for n in (1, 1000, 12345, 1 << 20):
+        p = lib.polsar_recommended_pitch(L.F32, n)
+        assert p >= n and (p * 4) % (64 << 10) == 32 << 10
+
+
 def test_status_strings(lib):
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.status_string(code) != "unknown status"

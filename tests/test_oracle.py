@@ -295,3 +295,29 @@ def test_wishart_gradient_vs_finite_differences():
     # FP64 oracle gradient against the __float128 one
     _, g64 = oracle.wishart(s, z, N)
     assert np.max(np.linalg.norm(g64 - gh, axis=0) / np.linalg.norm(gh, axis=0)) <= 1e-12
+
+
+# --------------------------------------------------------------- multilook
+def test_multilook_oracle():
+    """Z = (1/N) sum S S^H in __float128 against numpy (LAPACK-free einsum in
+    FP64), its trace identity, rank one for a single look (exactly, on
+    integer looks) and the generator's own FP64 multilook."""
+    img = synth.make_image(40, 30, 4, (2, 2), (1e-2, 1.0), 5, with_looks=True)
+    lk = img.looks.reshape(24, -1)
+    (zh, zl), mag = oracle.multilook128(lk, 4)
+    L4 = lk.reshape(4, 3, 2, -1)
+    S = L4[:, :, 0] + 1j * L4[:, :, 1]
+    Z = np.einsum("lim,ljm->mij", S, np.conj(S)) / 4
+    ref = synth.pack(Z)
+    assert np.all(np.abs(zh - ref) <= 8 * U64 * mag)
+    assert np.all(np.abs(zh - img.planes.reshape(9, -1)) <= 8 * U64 * mag)
+    tr = (np.abs(S) ** 2).sum(axis=(0, 1)) / 4
+    assert np.allclose(zh[0] + zh[1] + zh[2], tr, rtol=4 * U64)
+    assert np.all(mag >= np.abs(zh) * (1 - 1e-15))
+    rng = np.random.default_rng(21)
+    ints = rng.integers(-5, 6, size=(6, 200)).astype(np.float64)
+    (z1, z1l), _ = oracle.multilook128(ints, 1)
+    assert np.all(z1l == 0)
+    for i in range(0, 200, 20):
+        _, det = exact.inv_det(exact.unpack([int(v) for v in z1[:, i]]))
+        assert det == exact.Q(0)
