@@ -106,6 +106,20 @@ int polsar_multilook_inv_det(int dtype, int method, int precision, int64_t n, in
                              void* inv, int64_t inv_pitch, void* det, uint8_t* status,
                              unsigned long long* counters, void* stream);
 
+/* Block-diagonal pixels (closing section: multifrequency data, whose matrix
+ * is block diagonal with one Hermitian 3x3 block per band, each block
+ * inverted by the proposed method): n_blocks blocks per pixel.
+ *   z         in: 9*n_blocks planes; block b is planes 9b..9b+8 (pitch z_pitch)
+ *   inv       out (nullable): same layout; may be exactly z (in place)
+ *   det       out (nullable): product of the block determinants
+ *   block_det out (nullable): n_blocks planes (pitch block_det_pitch)
+ *   status    out (nullable): worst block status; counters count pixels.
+ * Each block's inverse and determinant are bitwise those of polsar_inv_det. */
+int polsar_blockdiag_inv_det(int dtype, int method, int precision, int64_t n, int n_blocks,
+                             const void* z, int64_t z_pitch, void* inv, int64_t inv_pitch,
+                             void* det, void* block_det, int64_t block_det_pitch,
+                             uint8_t* status, unsigned long long* counters, void* stream);
+
 typedef enum { POLSAR_FWD = 1, POLSAR_BWD = 2, POLSAR_FWD_BWD = 3 } polsar_pass;
 
 /* Wishart log-likelihood term, summed over pixels:
@@ -170,6 +184,23 @@ int polsar_batch_run(polsar_batch* b, void* stream);        /* one hipGraphLaunc
 int polsar_batch_run_eager(polsar_batch* b, void* stream);  /* same kernels, no graph */
 int64_t polsar_batch_tiles(const polsar_batch* b);
 void polsar_batch_destroy(polsar_batch* b);
+
+/* Out-of-core streaming (closing discussion of Section 4: images larger than
+ * device memory are streamed through the GPU piece by piece).  A streamer
+ * owns two device buffer sets of chunk_pixels pixels and two streams
+ * (allocated at creation, freed by destroy).  run() inverts n pixels held in
+ * HOST memory (z, inv, det, status are host pointers; pinned memory gives
+ * full PCIe speed; counters, if given, is a DEVICE pointer): chunk i is
+ * copied in, inverted and copied out on stream i % 2, so transfers of one
+ * chunk overlap the other's.  run() returns when all results are in host
+ * memory.  Results are bitwise those of polsar_inv_det. */
+typedef struct polsar_streamer polsar_streamer;
+int polsar_streamer_create(int dtype, int method, int precision, int64_t chunk_pixels,
+                           polsar_streamer** out);
+int polsar_streamer_run(polsar_streamer* s, int64_t n, const void* z, int64_t z_pitch,
+                        void* inv, int64_t inv_pitch, void* det, uint8_t* status,
+                        unsigned long long* counters);
+void polsar_streamer_destroy(polsar_streamer* s);
 
 /* Launch configuration of the per-call kernels, keyed by op (0 = inv_det,
  * 1 = wishart, 2 = multilook + inv_det), dtype, method, precision.

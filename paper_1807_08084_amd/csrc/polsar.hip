@@ -182,6 +182,80 @@ __global__ __launch_bounds__(256) void k_multilook(MultilookArgs a) {
   if (a.o.counters) flush_counters(a.o.counters, c0, c1, c2);
 }
 
+// ------------------------------------------------------------------ block diagonal
+// Pixels whose matrix is block diagonal with K Hermitian 3x3 blocks (several
+// frequency bands): each block is inverted on its own, the determinant is the
+// product of the block determinants, the status the worst block status.
+struct BlockArgs {
+  int k;            // blocks per pixel
+  void* bdet;       // optional per-block determinants: K planes, pitch bp
+  int64_t bp;
+  InvDetArgs o;     // z: 9K planes (block b at planes 9b..9b+8), inv likewise
+};
+
+template <class T, int OP, int V, bool NT>
+__global__ __launch_bounds__(256) void k_blockdiag(BlockArgs a) {
+  const T* __restrict__ Z = (const T*)a.o.z;
+  const int B = blockDim.x;
+  unsigned c0 = 0, c1 = 0, c2 = 0;
+  for (int64_t tile = blockIdx.x; tile < a.o.tiles; tile += gridDim.x) {
+    const int64_t v = tile * (int64_t)B + threadIdx.x;
+    if (v < a.o.nvec) {
+      T prod[V];
+      int worst[V];
+#pragma unroll
+      for (int l = 0; l < V; ++l) { prod[l] = T(1); worst[l] = 0; }
+      for (int b = 0; b < a.k; ++b) {
+        T in[9][V], out[9][V], dt[V];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) load_v<T, V, NT>(Z + (int64_t)(9 * b + k) * a.o.zp + v * V, in[k]);
+#pragma unroll
+        for (int l = 0; l < V; ++l) {
+          T zz[9], xx[9];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) zz[k] = in[k][l];
+          const int st = run_pixel<T, OP>(zz, xx, dt[l]);
+#pragma unroll
+          for (int k = 0; k < 9; ++k) out[k][l] = xx[k];
+          prod[l] *= dt[l];
+          worst[l] = st > worst[l] ? st : worst[l];
+        }
+        if (a.o.inv)
+#pragma unroll
+          for (int k = 0; k < 9; ++k) store_v<T, V, NT>((T*)a.o.inv + (int64_t)(9 * b + k) * a.o.ip + v * V, out[k]);
+        if (a.bdet) store_v<T, V, NT>((T*)a.bdet + (int64_t)b * a.bp + v * V, dt);
+      }
+#pragma unroll
+      for (int l = 0; l < V; ++l) tally(worst[l], c0, c1, c2);
+      if (a.o.det) store_v<T, V, NT>((T*)a.o.det + v * V, prod);
+      if (a.o.status) store_status<V>(a.o.status + v * V, worst);
+    }
+    if (V > 1 && tile == a.o.tiles - 1) {
+      const int64_t i = a.o.nvec * V + threadIdx.x;
+      if (i < a.o.n) {
+        T prod = T(1);
+        int worst = 0;
+        for (int b = 0; b < a.k; ++b) {
+          T zz[9], xx[9], dt;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) zz[k] = Z[(int64_t)(9 * b + k) * a.o.zp + i];
+          const int st = run_pixel<T, OP>(zz, xx, dt);
+          prod *= dt;
+          worst = st > worst ? st : worst;
+          if (a.o.inv)
+#pragma unroll
+            for (int k = 0; k < 9; ++k) ((T*)a.o.inv)[(int64_t)(9 * b + k) * a.o.ip + i] = xx[k];
+          if (a.bdet) ((T*)a.bdet)[(int64_t)b * a.bp + i] = dt;
+        }
+        tally(worst, c0, c1, c2);
+        if (a.o.det) ((T*)a.o.det)[i] = prod;
+        if (a.o.status) a.o.status[i] = (uint8_t)worst;
+      }
+    }
+  }
+  if (a.o.counters) flush_counters(a.o.counters, c0, c1, c2);
+}
+
 // ------------------------------------------------------------------ Wishart
 struct WishartArgs {
   const void* s;
@@ -517,6 +591,44 @@ hipError_t launch_multilook(int dtype, int op, const polsar_launch& c, bool vec,
   }
 }
 
+// ---- block-diagonal launch
+template <class T, int OP, int V>
+hipError_t dispatch_block_v(const polsar_launch& c, BlockArgs& a, hipStream_t s) {
+  a.o.nvec = a.o.n / V;
+  a.o.tiles = std::max<int64_t>(1, (a.o.nvec + c.block - 1) / c.block);
+  int64_t grid = a.o.tiles;
+  if (c.grid_per_cu > 0) grid = std::min<int64_t>(grid, (int64_t)c.grid_per_cu * device_cus());
+  if (c.nontemporal)
+    hipLaunchKernelGGL((k_blockdiag<T, OP, V, true>), dim3((unsigned)grid), dim3(c.block), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_blockdiag<T, OP, V, false>), dim3((unsigned)grid), dim3(c.block), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class T, int OP>
+hipError_t dispatch_block(const polsar_launch& c, bool vec, BlockArgs& a, hipStream_t s) {
+  constexpr int VW = 16 / sizeof(T);
+  return vec ? dispatch_block_v<T, OP, VW>(c, a, s) : dispatch_block_v<T, OP, 1>(c, a, s);
+}
+
+hipError_t launch_block(int dtype, int op, const polsar_launch& c, bool vec, BlockArgs& a, hipStream_t s) {
+  if (dtype == POLSAR_F32) {
+    switch (op) {
+      case ADJ_PLAIN: return dispatch_block<float, ADJ_PLAIN>(c, vec, a, s);
+      case ADJ_COMP: return dispatch_block<float, ADJ_COMP>(c, vec, a, s);
+      case ADJ_WIDE: return dispatch_block<float, ADJ_WIDE>(c, vec, a, s);
+      case CHOL_PLAIN: return dispatch_block<float, CHOL_PLAIN>(c, vec, a, s);
+      case CHOL_COMP: return dispatch_block<float, CHOL_COMP>(c, vec, a, s);
+      default: return dispatch_block<float, CHOL_WIDE>(c, vec, a, s);
+    }
+  }
+  switch (op) {
+    case ADJ_PLAIN: return dispatch_block<double, ADJ_PLAIN>(c, vec, a, s);
+    case ADJ_COMP: return dispatch_block<double, ADJ_COMP>(c, vec, a, s);
+    default: return dispatch_block<double, CHOL_PLAIN>(c, vec, a, s);
+  }
+}
+
 // ---- Wishart launch
 template <class T, int V, int U>
 hipError_t go_wishart(const polsar_launch& c, int64_t grid, WishartArgs& a, hipStream_t s) {
@@ -643,6 +755,42 @@ int polsar_multilook_inv_det(int dtype, int method, int precision, int64_t n, in
   const polsar_launch c = get_cfg(2, dtype, method, precision);
   if (launch_multilook(dtype, op_code(method, precision), c, vec, a, (hipStream_t)stream) != hipSuccess)
     return POLSAR_E_HIP;
+  return POLSAR_OK;
+}
+
+int polsar_blockdiag_inv_det(int dtype, int method, int precision, int64_t n, int n_blocks, const void* z,
+                             int64_t z_pitch, void* inv, int64_t inv_pitch, void* det, void* block_det,
+                             int64_t block_det_pitch, uint8_t* status, unsigned long long* counters, void* stream) {
+  int r = check_mode(dtype, method, precision);
+  if (r) return r;
+  if (n < 0 || n_blocks < 1 || n_blocks > 1024) return POLSAR_E_ARG;
+  const size_t es = esize(dtype);
+  if ((r = check_planes(z, z_pitch, n, es))) return r;
+  if (inv && (r = check_planes(inv, inv_pitch, n, es))) return r;
+  if (block_det && (r = check_planes(block_det, block_det_pitch, n, es))) return r;
+  if (det && ((uintptr_t)det % es)) return POLSAR_E_ALIGN;
+  if (counters && ((uintptr_t)counters % 8)) return POLSAR_E_ALIGN;
+  if (!inv && !det && !block_det && !status && !counters) return POLSAR_E_ARG;
+  if (n > 0) {
+    const int P = 9 * n_blocks;
+    const Range rz = span(z, P, z_pitch, n, es);
+    const Range ri = inv ? span(inv, P, inv_pitch, n, es) : Range{0, 0};
+    const Range rd = det ? span(det, 1, n, n, es) : Range{0, 0};
+    const Range rb = block_det ? span(block_det, n_blocks, block_det_pitch, n, es) : Range{0, 0};
+    const Range rs = status ? span(status, 1, n, n, 1) : Range{0, 0};
+    const Range all[5] = {rz, ri, rd, rb, rs};
+    for (int p = 0; p < 5; ++p)
+      for (int q = p + 1; q < 5; ++q) {
+        if (p == 0 && q == 1 && inv == z && inv_pitch == z_pitch) continue;  // in place
+        if (all[p].hi > all[p].lo && all[q].hi > all[q].lo && overlap(all[p], all[q])) return POLSAR_E_ALIAS;
+      }
+  }
+  if (n == 0) return POLSAR_OK;
+  BlockArgs a{n_blocks, block_det, block_det_pitch, InvDetArgs{z, z_pitch, inv, inv_pitch, det, status, counters, n, 0, 0}};
+  const bool vec = vec_ok(z, z_pitch, es) && vec_ok(inv, inv_pitch, es) && vec_ok(det, 0, es) &&
+                   vec_ok(block_det, block_det_pitch, es) && (status == nullptr || ((uintptr_t)status % (16 / es)) == 0);
+  const polsar_launch c = get_cfg(0, dtype, method, precision);
+  if (launch_block(dtype, op_code(method, precision), c, vec, a, (hipStream_t)stream) != hipSuccess) return POLSAR_E_HIP;
   return POLSAR_OK;
 }
 
@@ -791,5 +939,106 @@ int polsar_stream_copy(int dtype, int64_t n, const void* src, int64_t src_pitch,
 #undef POLSAR_COPY
   return hipGetLastError() == hipSuccess ? POLSAR_OK : POLSAR_E_HIP;
 }
+
+
+// ------------------------------------------------------------------ out-of-core streaming
+// Host-resident images (larger than device memory, or simply on the host):
+// the pixels are cut into chunks; chunk i uses device buffer set i % 2 and
+// stream i % 2: one 2-D copy of its 9 input plane segments host -> device,
+// the inverse kernel, and 2-D copies of the 9 inverse planes, the det and
+// the status segments back.  Work on the two streams overlaps, so the copy
+// of one chunk runs while the other is computed.
+}  // extern "C"
+
+struct polsar_streamer {
+  int dtype, method, precision;
+  int64_t chunk, pitch;  // device plane pitch (elements) of each buffer set
+  void* dz[2];
+  void* dout[2];  // 9 inverse planes + det plane
+  uint8_t* dst[2];
+  hipStream_t st[2];
+};
+
+namespace {
+void streamer_release(polsar_streamer* s) {
+  if (!s) return;
+  for (int b = 0; b < 2; ++b) {
+    if (s->st[b]) (void)hipStreamDestroy(s->st[b]);
+    if (s->dz[b]) (void)hipFree(s->dz[b]);
+    if (s->dout[b]) (void)hipFree(s->dout[b]);
+    if (s->dst[b]) (void)hipFree(s->dst[b]);
+  }
+  delete s;
+}
+}  // namespace
+
+extern "C" {
+
+int polsar_streamer_create(int dtype, int method, int precision, int64_t chunk_pixels, polsar_streamer** out) {
+  if (!out) return POLSAR_E_ARG;
+  *out = nullptr;
+  int r = check_mode(dtype, method, precision);
+  if (r) return r;
+  if (chunk_pixels < 1 || chunk_pixels > ((int64_t)1 << 34)) return POLSAR_E_ARG;
+  polsar_streamer* s = new polsar_streamer();
+  s->dtype = dtype;
+  s->method = method;
+  s->precision = precision;
+  s->chunk = chunk_pixels;
+  s->pitch = polsar_recommended_pitch(dtype, chunk_pixels);
+  const size_t es = esize(dtype);
+  for (int b = 0; b < 2; ++b) {
+    if (hipMalloc(&s->dz[b], 9 * s->pitch * es) != hipSuccess || hipMalloc(&s->dout[b], 10 * s->pitch * es) != hipSuccess ||
+        hipMalloc((void**)&s->dst[b], (size_t)chunk_pixels) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->st[b], hipStreamNonBlocking) != hipSuccess) {
+      streamer_release(s);
+      return POLSAR_E_HIP;
+    }
+  }
+  *out = s;
+  return POLSAR_OK;
+}
+
+int polsar_streamer_run(polsar_streamer* s, int64_t n, const void* z, int64_t z_pitch, void* inv, int64_t inv_pitch,
+                        void* det, uint8_t* status, unsigned long long* counters) {
+  if (!s) return POLSAR_E_ARG;
+  if (n < 0) return POLSAR_E_ARG;
+  const size_t es = esize(s->dtype);
+  int r = check_planes(z, z_pitch, n, es);
+  if (r) return r;
+  if (inv && (r = check_planes(inv, inv_pitch, n, es))) return r;
+  if (det && ((uintptr_t)det % es)) return POLSAR_E_ALIGN;
+  if (!inv && !det && !status && !counters) return POLSAR_E_ARG;
+  if (counters && ((uintptr_t)counters % 8)) return POLSAR_E_ALIGN;
+  if (n > 0) {
+    const Range rz = span(z, 9, z_pitch, n, es);
+    if (inv && overlap(span(inv, 9, inv_pitch, n, es), rz)) return POLSAR_E_ALIAS;
+    if (det && overlap(span(det, 1, n, n, es), rz)) return POLSAR_E_ALIAS;
+  }
+  const polsar_launch c = get_cfg(0, s->dtype, s->method, s->precision);
+  const int op = op_code(s->method, s->precision);
+  const size_t P = (size_t)s->pitch * es;
+  hipError_t e = hipSuccess;
+  for (int64_t off = 0, i = 0; off < n && e == hipSuccess; off += s->chunk, ++i) {
+    const int b = (int)(i & 1);
+    const int64_t m = std::min<int64_t>(s->chunk, n - off);
+    hipStream_t st = s->st[b];
+    const size_t w = (size_t)m * es;
+    e = hipMemcpy2DAsync(s->dz[b], P, (const char*)z + off * es, (size_t)z_pitch * es, w, 9, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) break;
+    InvDetArgs a{s->dz[b], s->pitch, inv ? s->dout[b] : nullptr, s->pitch,
+                 det ? (char*)s->dout[b] + 9 * P : nullptr, status ? s->dst[b] : nullptr, counters, m, 0, 0};
+    e = launch_inv_det(s->dtype, op, c, true, a, st);
+    if (e != hipSuccess) break;
+    if (inv) e = hipMemcpy2DAsync((char*)inv + off * es, (size_t)inv_pitch * es, s->dout[b], P, w, 9, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && det) e = hipMemcpyAsync((char*)det + off * es, (char*)s->dout[b] + 9 * P, w, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && status) e = hipMemcpyAsync(status + off, s->dst[b], (size_t)m, hipMemcpyDeviceToHost, st);
+  }
+  const hipError_t e0 = hipStreamSynchronize(s->st[0]);
+  const hipError_t e1 = hipStreamSynchronize(s->st[1]);
+  return (e == hipSuccess && e0 == hipSuccess && e1 == hipSuccess) ? POLSAR_OK : POLSAR_E_HIP;
+}
+
+void polsar_streamer_destroy(polsar_streamer* s) { streamer_release(s); }
 
 }  // extern "C"

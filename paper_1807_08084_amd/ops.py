@@ -128,6 +128,68 @@ def multilook_inv_det(looks: torch.Tensor, n_looks: int, method: str = "adjugate
     return z, inv, det, st
 
 
+def blockdiag_inv_det(z: torch.Tensor, n_blocks: int, method: str = "adjugate", precision: str = "compensated",
+                      *, block_det: bool = False, status: bool = False, counters: torch.Tensor | None = None,
+                      stream=None):
+    """Block-diagonal pixels: z (9K, ...) -> (inv (9K, ...), det product, block dets or None, status or None)."""
+    dt = _dtype_code(z)
+    if z.dim() < 2 or z.shape[0] != 9 * n_blocks or not z.is_cuda or not z[0].is_contiguous():
+        raise ValueError(f"z must be GPU planes of shape (9*{n_blocks}, ...)")
+    shape = z.shape[1:]
+    n, zp = z[0].numel(), z.stride(0)
+    out = empty_planes(9 * n_blocks + 1, shape, z.dtype, z.device)
+    inv, det = out[:9 * n_blocks], out[9 * n_blocks]
+    bd = empty_planes(n_blocks, shape, z.dtype, z.device) if block_det else None
+    st = torch.empty(shape, dtype=torch.uint8, device=z.device) if status else None
+    rc = L.lib().polsar_blockdiag_inv_det(dt, _METHODS[method], _PRECS[precision], n, int(n_blocks), _ptr(z), zp,
+                                          _ptr(inv), inv.stride(0), _ptr(det), _ptr(bd),
+                                          bd.stride(0) if bd is not None else 0, _ptr(st), _ptr(counters),
+                                          _stream(stream))
+    L.check(rc, "polsar_blockdiag_inv_det")
+    return inv, det, bd, st
+
+
+class Streamer:
+    """Out-of-core inverse/determinant of host-resident planes, chunk by chunk
+    through two device buffer sets and two streams (polsar_streamer_*)."""
+
+    def __init__(self, dtype: torch.dtype, chunk_pixels: int, method: str = "adjugate",
+                 precision: str = "compensated"):
+        self.dtype = dtype
+        self._h = ctypes.c_void_p()
+        L.check(L.lib().polsar_streamer_create(L.F32 if dtype == torch.float32 else L.F64, _METHODS[method],
+                                               _PRECS[precision], int(chunk_pixels), ctypes.byref(self._h)),
+                "polsar_streamer_create")
+
+    def run(self, z: torch.Tensor, inv: torch.Tensor | None = None, det: torch.Tensor | None = None,
+            status: torch.Tensor | None = None, counters: torch.Tensor | None = None):
+        """z: (9, ...) CPU planes (pinned for full speed); outputs CPU tensors,
+        allocated pinned when not given.  Synchronous."""
+        if z.is_cuda or z.dtype != self.dtype or z.shape[0] != 9 or not z[0].is_contiguous():
+            raise ValueError("z must be CPU planes (9, ...) of the streamer's dtype")
+        shape = z.shape[1:]
+        n = z[0].numel()
+        if inv is None:
+            inv = torch.empty((9,) + tuple(shape), dtype=z.dtype, pin_memory=True)
+        if det is None:
+            det = torch.empty(shape, dtype=z.dtype, pin_memory=True)
+        rc = L.lib().polsar_streamer_run(self._h, n, _ptr(z), z.stride(0), _ptr(inv), inv.stride(0), _ptr(det),
+                                         _ptr(status), _ptr(counters))
+        L.check(rc, "polsar_streamer_run")
+        return inv, det, status
+
+    def close(self):
+        if self._h:
+            L.lib().polsar_streamer_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def workspace_bytes(dtype: torch.dtype, n: int) -> int:
     return int(L.lib().polsar_wishart_workspace_bytes(L.F32 if dtype == torch.float32 else L.F64, n))
 

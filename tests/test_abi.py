@@ -1,5 +1,8 @@
 """The C-ABI library loads, exports every declared symbol, and rejects bad
-arguments before any HIP call (no GPU needed: no compute call is made)."""
+arguments before any HIP call (no GPU needed: no compute call is made).
+
+Every call below either fails validation or has n == 0, so none reaches a
+kernel launch: the stand-in addresses are never dereferenced."""
 import ctypes
 
 import pytest
@@ -120,3 +123,21 @@ def test_batch_and_copy_argument_errors(lib):
     assert lib.polsar_stream_copy(L.F32, 100, FAKE, 100, 5, FAKE2, 100, 10, None) == L.E_UNSUPPORTED
     assert lib.polsar_stream_copy(L.F32, 100, FAKE, 100, 9, FAKE + 64, 100, 10, None) == L.E_ALIAS
     assert lib.polsar_stream_copy(L.F32, 0, FAKE, 100, 9, FAKE2, 100, 10, None) == L.OK
+
+
+def test_multilook_blockdiag_streamer_argument_errors(lib):
+    ml = lib.polsar_multilook_inv_det
+    assert ml(L.F32, L.ADJUGATE, L.COMPENSATED, 100, 0, FAKE, 100, None, 0, FAKE2, 100, FAKE3, None, None, None) == L.E_ARG
+    assert ml(L.F32, L.ADJUGATE, L.COMPENSATED, 100, 4, FAKE, 99, None, 0, FAKE2, 100, FAKE3, None, None, None) == L.E_ARG
+    assert ml(L.F64, L.ADJUGATE, L.WIDE, 100, 4, FAKE, 100, None, 0, FAKE2, 100, FAKE3, None, None, None) == L.E_UNSUPPORTED
+    assert ml(L.F32, L.ADJUGATE, L.COMPENSATED, 100, 4, FAKE, 100, None, 0, FAKE + 400, 100, FAKE3, None, None, None) == L.E_ALIAS
+    assert ml(L.F32, L.ADJUGATE, L.COMPENSATED, 100, 4, FAKE, 100, None, 0, None, 0, None, None, None, None) == L.E_ARG
+    assert ml(L.F32, L.ADJUGATE, L.COMPENSATED, 0, 4, FAKE, 100, None, 0, FAKE2, 100, FAKE3, None, None, None) == L.OK
+    bd = lib.polsar_blockdiag_inv_det
+    assert bd(L.F32, L.ADJUGATE, L.COMPENSATED, 100, 0, FAKE, 100, FAKE2, 100, FAKE3, None, 0, None, None, None) == L.E_ARG
+    assert bd(L.F32, L.ADJUGATE, L.COMPENSATED, 100, 2, FAKE, 100, FAKE + 800, 100, FAKE3, None, 0, None, None, None) == L.E_ALIAS
+    assert bd(L.F32, L.ADJUGATE, L.COMPENSATED, 0, 2, FAKE, 100, FAKE, 100, FAKE3, None, 0, None, None, None) == L.OK
+    h = ctypes.c_void_p()
+    assert lib.polsar_streamer_create(L.F32, L.ADJUGATE, L.COMPENSATED, 0, ctypes.byref(h)) == L.E_ARG
+    assert lib.polsar_streamer_create(L.F64, L.ADJUGATE, L.WIDE, 1024, ctypes.byref(h)) == L.E_UNSUPPORTED
+    assert lib.polsar_streamer_run(None, 10, FAKE, 10, FAKE2, 10, FAKE3, None, None) == L.E_ARG
