@@ -92,6 +92,68 @@ def cpu_baseline(z64: np.ndarray, n_px: int, min_seconds: float = 10.0):
                       f"{n_px}-pixel image, {passes} passes, {el:.1f} s"}
 
 
+def other_workloads(torch, ops, dev, steps):
+    """Each remaining workload timed on its own input (device time, data resident)."""
+    from paper_1807_08084_amd import synth
+    from paper_1807_08084_amd.batch import BatchPlan
+    res = {}
+    # precision: 8192^2, N=3, per-pixel Sigma, lam in [1e-8, 1]; FP32 compensated with reroute
+    img = synth.workload_precision()
+    z = ops.upload_planes(img.planes.reshape(9, -1).astype(np.float32), torch.float32, dev)
+    n = z.shape[1]
+    del img
+    o = ops.empty_planes(10, n, torch.float32, dev)
+    ctr = torch.zeros(3, dtype=torch.int64, device=dev)
+    ops.inv_det(z, "adjugate", "compensated", inv=o[:9], det=o[9], counters=ctr)
+    for prec in ("compensated", "plain", "wide"):
+        ms = time_calls(lambda: ops.inv_det(z, "adjugate", prec, inv=o[:9], det=o[9]), steps, 3, torch)
+        res[f"precision_8192_adjugate_{prec}_f32"] = {"gpx_s": round(n / ms / 1e6, 3), "ms": round(ms, 4),
+                                                      "GB_s": round(76 * n / ms / 1e6, 1)}
+    res["precision_8192_rerouted_fraction"] = round(int(ctr[1].item()) / n, 4)
+    print(f"# precision workload done", file=sys.stderr, flush=True)
+    del z, o
+    # Wishart: 2048^2, N=8; fused forward + backward
+    img, sig = synth.workload_wishart()
+    n = img.planes[0].size
+    for dt, tn, bpp in ((torch.float32, "f32", 108), (torch.float64, "f64", 216)):
+        zt = ops.upload_planes(img.planes.reshape(9, -1), dt, dev)
+        st = ops.upload_planes(sig.reshape(9, -1), dt, dev)
+        ws = torch.empty(ops.workspace_bytes(dt, n) // 8 + 1, dtype=torch.float64, device=dev)
+        ms = time_calls(lambda: ops.wishart_loglik(st, zt, 8.0, forward=True, backward=True, workspace=ws),
+                        steps, 3, torch)
+        res[f"wishart_2048_fwd_bwd_{tn}"] = {"gpx_s": round(n / ms / 1e6, 3), "ms": round(ms, 4),
+                                             "GB_s": round(bpp * n / ms / 1e6, 1)}
+        del zt, st, ws
+    print(f"# wishart workload done", file=sys.stderr, flush=True)
+    # batch: 64 images, FP32 compensated inverse + Wishart fwd + bwd, one graph vs per-image loop
+    imgs = synth.workload_batch()
+    items = []
+    for im in imgs:
+        zf = im.planes.reshape(9, -1)
+        items.append({"z": ops.upload_planes(zf, torch.float32, dev),
+                      "sigma": ops.upload_planes(synth.wishart_sigma0(zf), torch.float32, dev),
+                      "n_looks": float(im.n_looks)})
+    del imgs
+    n = sum(it["z"].shape[1] for it in items)
+    plan = BatchPlan(items, "adjugate", "compensated", status=False)
+    g_ms = time_calls(plan.run, steps, 3, torch)
+    ws = torch.empty(ops.workspace_bytes(torch.float32, max(it["z"].shape[1] for it in items)) // 8 + 1,
+                     dtype=torch.float64, device=dev)
+    outs = [(ops.empty_planes(10, it["z"].shape[1], torch.float32, dev)) for it in items]
+
+    def loop():
+        for it, ob in zip(items, outs):
+            ops.inv_det(it["z"], "adjugate", "compensated", inv=ob[:9], det=ob[9])
+            ops.wishart_loglik(it["sigma"], it["z"], it["n_looks"], forward=True, backward=True, workspace=ws)
+    l_ms = time_calls(loop, steps, 3, torch)
+    res["batch_64_images"] = {"pixels": n, "graph_ms": round(g_ms, 4), "loop_ms": round(l_ms, 4),
+                              "graph_gpx_s": round(n / g_ms / 1e6, 3), "loop_gpx_s": round(n / l_ms / 1e6, 3),
+                              "graph_GB_s": round(148 * n / g_ms / 1e6, 1),
+                              "ops": "inverse+det of Z, Wishart fwd+bwd of S against Z (FP32 compensated)"}
+    plan.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +162,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-rows", action="store_true")
     ap.add_argument("--tune", action="store_true", help="autotune the launch before timing")
+    ap.add_argument("--workloads", action="store_true",
+                    help="also time the precision (8192^2), Wishart (2048^2) and 64-image batch workloads")
     ap.add_argument("--probe", action="store_true",
                     help="after the timed steps, run a one-plane copy of the same pixel count "
                          "(known bytes: calibrates the HBM traffic counters)")
@@ -229,6 +293,8 @@ def main():
             "f32_equal_accuracy_vs_cholesky_wide": round(rows["cholesky_wide_f32"]["ms"] / adj, 3),
             "f64_plain": round(rows["cholesky_plain_f64"]["ms"] / rows["adjugate_plain_f64"]["ms"], 3),
             "paper_context": "about 2.2x on a GeForce 940M, OpenCL (Table 2)"}
+    if args.workloads:
+        out["workloads"] = other_workloads(torch, ops, dev, max(10, args.steps // 4))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(z64.astype(np.float32).astype(np.float64), n_px)
     print(json.dumps(out), flush=True)
