@@ -230,7 +230,10 @@ constexpr float REROUTE_REL = 1e-6f;
 // exceeds REROUTE_REL * |det|, or whose det is not positive or not finite,
 // is recomputed by the compensated FP64 path from its exactly widened
 // inputs and rounded to FP32 (status ST_REROUTED when that succeeds).
-PX_HD int adjugate_comp(const float z[9], float x[9], float& det, float* bound_out = nullptr) {
+//
+// adjugate_comp_try: the FP32 step; returns true and the result when the
+// pixel is accepted, false when it must be recomputed.
+PX_HD bool adjugate_comp_try(const float z[9], float x[9], float& det, float* bound_out = nullptr) {
   DW<float> c[9];
   float mag[9], bound;
   cofactors_comp(z, c, mag);
@@ -238,10 +241,12 @@ PX_HD int adjugate_comp(const float z[9], float x[9], float& det, float* bound_o
   if (bound_out) *bound_out = bound;
   const float t = 1.0f / det;
   const bool ok = det > 0.0f && finite_(det) && finite_(t) && !(bound > REROUTE_REL * det);
-  if (ok) {
-    scale_comp(c, t, x);
-    return ST_OK;
-  }
+  if (ok) scale_comp(c, t, x);
+  return ok;
+}
+
+// adjugate_comp_reroute: the FP64 recompute of one pixel, rounded to FP32.
+PX_HD int adjugate_comp_reroute(const float z[9], float x[9], float& det) {
   double zd[9], xd[9], dd;
 #pragma unroll
   for (int k = 0; k < 9; ++k) zd[k] = (double)z[k];
@@ -254,6 +259,11 @@ PX_HD int adjugate_comp(const float z[9], float x[9], float& det, float* bound_o
     if (st == ST_OK) st = ST_REROUTED;
   }
   return st;
+}
+
+PX_HD int adjugate_comp(const float z[9], float x[9], float& det, float* bound_out = nullptr) {
+  if (adjugate_comp_try(z, x, det, bound_out)) return ST_OK;
+  return adjugate_comp_reroute(z, x, det);
 }
 
 // ---------------------------------------------------------------------------

@@ -15,6 +15,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/polsar.h"
@@ -36,21 +37,117 @@ struct InvDetArgs {
   int64_t tiles;  // ceil(nvec / (block * U)), at least 1
 };
 
+// Compensated FP32 for one lane's V pixels with the FP64 recomputes gathered
+// across the wave: every pixel first takes the FP32 step; the pixels it
+// rejects are queued in this wave's LDS region (their 9 inputs), the wave's
+// lanes take one queued pixel each through the FP64 step, and the results go
+// back through LDS to the owning lanes.  A wave with nothing rejected skips
+// the queue.  With a fraction p of pixels rejected the FP64 step runs
+// ceil(64 V p / 64) times per wave instead of up to V times.
+// Queue: 64*V entries of REQ_FLOATS floats (9 inputs, then 9 outputs + det),
+// then 64*V status bytes.
+constexpr int REQ_FLOATS = 10;
+
+template <int V>
+__device__ __forceinline__ void comp_f32_wave(const float (&in)[9][V], float (&out)[9][V], float (&dt)[V],
+                                              int (&st)[V], float* q, uint8_t* qs) {
+  bool need[V];
+#pragma unroll
+  for (int l = 0; l < V; ++l) {
+    float zz[9], xx[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) zz[k] = in[k][l];
+    need[l] = !px::adjugate_comp_try(zz, xx, dt[l]);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) out[k][l] = xx[k];
+    st[l] = px::ST_OK;
+  }
+  unsigned long long mask[V];
+  int total = 0;
+#pragma unroll
+  for (int l = 0; l < V; ++l) {
+    mask[l] = __ballot(need[l]);
+    total += __popcll(mask[l]);
+  }
+  if (total == 0) return;  // uniform across the active lanes
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = lane == 0 ? 0ull : ((1ull << lane) - 1ull);
+  // the active lanes share the queue: rank among them, stride = their count
+  const unsigned long long active = __ballot(1);
+  const int rank = __popcll(active & below), nact = __popcll(active);
+  int base = 0;
+#pragma unroll
+  for (int l = 0; l < V; ++l) {
+    if (need[l]) {
+      const int pos = base + __popcll(mask[l] & below);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) q[pos * REQ_FLOATS + k] = in[k][l];
+    }
+    base += __popcll(mask[l]);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int e = rank; e < total; e += nact) {
+    float zz[9], xx[9], d;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) zz[k] = q[e * REQ_FLOATS + k];
+    const int sst = px::adjugate_comp_reroute(zz, xx, d);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) q[e * REQ_FLOATS + k] = xx[k];
+    q[e * REQ_FLOATS + 9] = d;
+    qs[e] = (uint8_t)sst;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  base = 0;
+#pragma unroll
+  for (int l = 0; l < V; ++l) {
+    if (need[l]) {
+      const int pos = base + __popcll(mask[l] & below);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) out[k][l] = q[pos * REQ_FLOATS + k];
+      dt[l] = q[pos * REQ_FLOATS + 9];
+      st[l] = qs[pos];
+    }
+    base += __popcll(mask[l]);
+  }
+}
+
+// LDS bytes of the FP32 compensated queue for one block.
+inline size_t comp_queue_bytes(int block, int v) {
+  const size_t entries = (size_t)block * v;  // 64*V per wave, block/64 waves
+  return entries * (REQ_FLOATS * sizeof(float) + 1);
+}
+
 // One pixel-vector of the inverse/determinant: load done by the caller.
-template <class T, int OP, int V, bool NT>
+// COMPACT: the FP32 compensated form with the wave-level FP64 queue (needs
+// the block's dynamic LDS); otherwise the per-pixel function inline.
+template <class T, int OP, int V, bool NT, bool COMPACT = false>
 __device__ __forceinline__ void inv_det_vec(const InvDetArgs& a, const T (&in)[9][V], int64_t v,
                                             unsigned& c0, unsigned& c1, unsigned& c2) {
   T out[9][V], dt[V];
   int st[V];
+  if constexpr (COMPACT) {
+    extern __shared__ __align__(16) float polsar_dyn_lds[];
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    float* q = polsar_dyn_lds + (size_t)w * 64 * V * REQ_FLOATS;
+    uint8_t* qs = (uint8_t*)(polsar_dyn_lds + (size_t)nw * 64 * V * REQ_FLOATS) + w * 64 * V;
+    comp_f32_wave<V>(in, out, dt, st, q, qs);
 #pragma unroll
-  for (int l = 0; l < V; ++l) {
-    T zz[9], xx[9];
+    for (int l = 0; l < V; ++l) tally(st[l], c0, c1, c2);
+  } else {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) zz[k] = in[k][l];
-    st[l] = run_pixel<T, OP>(zz, xx, dt[l]);
+    for (int l = 0; l < V; ++l) {
+      T zz[9], xx[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) out[k][l] = xx[k];
-    tally(st[l], c0, c1, c2);
+      for (int k = 0; k < 9; ++k) zz[k] = in[k][l];
+      st[l] = run_pixel<T, OP>(zz, xx, dt[l]);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) out[k][l] = xx[k];
+      tally(st[l], c0, c1, c2);
+    }
   }
   const int64_t e = v * V;
   if (a.inv) {
@@ -81,7 +178,7 @@ __global__ __launch_bounds__(256) void k_inv_det(InvDetArgs a) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t v = v0 + (int64_t)u * B;
-      if (v < a.nvec) inv_det_vec<T, OP, V, NT>(a, in[u], v, c0, c1, c2);
+      if (v < a.nvec) inv_det_vec<T, OP, V, NT, OP == ADJ_COMP && std::is_same<T, float>::value>(a, in[u], v, c0, c1, c2);
     }
     if (V > 1 && tile == a.tiles - 1) {
       // the n mod V pixels after the last full vector, one per lane
@@ -456,23 +553,31 @@ int op_code(int method, int prec) {
 // Launch helpers: pick the template instance for (V, U, NT).
 template <class T, int OP, int V, int U>
 hipError_t go_inv_det(const polsar_launch& c, int64_t grid, InvDetArgs& a, hipStream_t s) {
+  const size_t lds = (OP == ADJ_COMP && std::is_same<T, float>::value) ? comp_queue_bytes(c.block, V) : 0;
   if (c.nontemporal)
-    hipLaunchKernelGGL((k_inv_det<T, OP, V, U, true>), dim3((unsigned)grid), dim3(c.block), 0, s, a);
+    hipLaunchKernelGGL((k_inv_det<T, OP, V, U, true>), dim3((unsigned)grid), dim3(c.block), lds, s, a);
   else
-    hipLaunchKernelGGL((k_inv_det<T, OP, V, U, false>), dim3((unsigned)grid), dim3(c.block), 0, s, a);
+    hipLaunchKernelGGL((k_inv_det<T, OP, V, U, false>), dim3((unsigned)grid), dim3(c.block), lds, s, a);
   return hipGetLastError();
 }
 
 template <class T, int OP, int V>
 hipError_t dispatch_inv_det_v(const polsar_launch& c, InvDetArgs& a, hipStream_t s) {
   a.nvec = a.n / V;
-  const int64_t per_tile = (int64_t)c.block * c.unroll;
+  const int unroll = (c.unroll == 4 && OP == ADJ_COMP && std::is_same<T, float>::value) ? 2 : c.unroll;
+  const int64_t per_tile = (int64_t)c.block * unroll;
   a.tiles = std::max<int64_t>(1, (a.nvec + per_tile - 1) / per_tile);
   int64_t grid = a.tiles;
   if (c.grid_per_cu > 0) grid = std::min<int64_t>(grid, (int64_t)c.grid_per_cu * device_cus());
   if (c.unroll == 1) return go_inv_det<T, OP, V, 1>(c, grid, a, s);
-  if (c.unroll == 2) return go_inv_det<T, OP, V, 2>(c, grid, a, s);
-  return go_inv_det<T, OP, V, 4>(c, grid, a, s);
+  // the compensated FP32 kernel with four vectors per lane runs out of
+  // registers; unroll 4 is taken as 2 there (the tile size follows)
+  if constexpr (OP == ADJ_COMP && std::is_same<T, float>::value) {
+    return go_inv_det<T, OP, V, 2>(c, grid, a, s);
+  } else {
+    if (c.unroll == 2) return go_inv_det<T, OP, V, 2>(c, grid, a, s);
+    return go_inv_det<T, OP, V, 4>(c, grid, a, s);
+  }
 }
 
 // Access width: 16 bytes per lane per plane (V = 16 / sizeof(T) pixels),
