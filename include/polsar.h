@@ -70,7 +70,10 @@ typedef enum { POLSAR_ADJUGATE = 0, POLSAR_CHOLESKY = 1 } polsar_method;
  *   WIDE         F32 storage, F64 arithmetic (F32 only). */
 typedef enum { POLSAR_PLAIN = 0, POLSAR_COMPENSATED = 1, POLSAR_WIDE = 2 } polsar_precision;
 
-/* Per-pixel status values. */
+/* Per-pixel status values.  NOT_PD: the matrix is not positive definite —
+ * adjugate forms test the leading principal minors a, a d - |b|^2 and det
+ * (Sylvester's criterion; all three are by-products of Alg. 2), Cholesky
+ * forms the squared pivots.  NONFINITE: an input or a result is Inf/NaN. */
 enum { POLSAR_PX_OK = 0, POLSAR_PX_REROUTED = 1, POLSAR_PX_NOT_PD = 2, POLSAR_PX_NONFINITE = 3 };
 
 /* Inverse and determinant of n packed Hermitian matrices (Alg. 2, Section
@@ -174,7 +177,8 @@ typedef struct polsar_batch polsar_batch;
 
 /* Allocates device tables, a workspace and the graph (the only call that
  * allocates).  method: POLSAR_ADJUGATE or POLSAR_CHOLESKY for the inverse;
- * grid_per_cu 0 = tuned default.  Returns POLSAR_OK and *out, or an error
+ * the launch shape is the op-3 entry of the launch table, grid_per_cu > 0
+ * overrides its blocks per compute unit.  Returns POLSAR_OK and *out, or an error
  * (no allocation left behind). */
 int polsar_batch_create(const polsar_image* imgs, int count, int dtype, int method,
                         int precision, unsigned ops, const double* grad_loss,
@@ -202,15 +206,20 @@ int polsar_streamer_run(polsar_streamer* s, int64_t n, const void* z, int64_t z_
                         unsigned long long* counters);
 void polsar_streamer_destroy(polsar_streamer* s);
 
-/* Launch configuration of the per-call kernels, keyed by op (0 = inv_det,
- * 1 = wishart, 2 = multilook + inv_det), dtype, method, precision.
+/* Launch configuration of the kernels, keyed by op (0 = inv_det,
+ * 1 = wishart, 2 = multilook + inv_det, 3 = batch; ops 2 and 3 take unroll
+ * 1, op 3 a persistent grid), dtype, method, precision.
  *   block        threads per block: 64, 128 or 256
  *   unroll       128-bit vectors per thread per tile: 1, 2 or 4
  *   grid_per_cu  0 = one tile per block; k > 0 = persistent grid of k blocks
  *                per compute unit striding over tiles
  *   nontemporal  1 = streaming (non-temporal) loads and stores
- *   vector_bytes 16 or 8: bytes per lane per plane access on aligned planes */
-typedef struct { int block, unroll, grid_per_cu, nontemporal, vector_bytes; } polsar_launch;
+ *   vector_bytes 16 or 8: bytes per lane per plane access on aligned planes
+ *   blocks_per_cu 0 = as many resident blocks as registers allow; k > 0 = at
+ *                most k blocks resident per compute unit (enforced by padding
+ *                the block's LDS).  On MI355X these streaming kernels move
+ *                more bytes per second with few waves in flight per CU. */
+typedef struct { int block, unroll, grid_per_cu, nontemporal, vector_bytes, blocks_per_cu; } polsar_launch;
 int polsar_get_launch(int op, int dtype, int method, int precision, polsar_launch* out);
 int polsar_set_launch(int op, int dtype, int method, int precision, const polsar_launch* cfg);
 

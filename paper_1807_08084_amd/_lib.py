@@ -27,7 +27,7 @@ class PolsarError(RuntimeError):
 class Launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int), ("unroll", ctypes.c_int),
                 ("grid_per_cu", ctypes.c_int), ("nontemporal", ctypes.c_int),
-                ("vector_bytes", ctypes.c_int)]
+                ("vector_bytes", ctypes.c_int), ("blocks_per_cu", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -11,9 +11,10 @@
 // do not depend on the grid.  Both launches are captured in one HIP graph at
 // creation; running the batch is one graph launch.
 //
-// The tile cut and the per-pixel functions are those of the per-call
-// kernels at unroll 1, so every per-pixel output is bitwise equal to a
-// per-image call with the same block size.
+// The per-pixel functions are those of the per-call kernels, so every
+// per-pixel output is bitwise equal to a per-image call; the per-image loss
+// equals the per-call Wishart loss bitwise when both cut tiles alike (same
+// block size and access width, unroll 1), and to rounding otherwise.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,6 +22,8 @@
 
 #include "../../include/polsar.h"
 #include "common.hpp"
+
+size_t polsar_launch_lds_bytes(const polsar_launch& c, size_t need);
 
 namespace {
 using namespace polsar_dev;
@@ -190,6 +193,7 @@ struct polsar_batch {
   unsigned ops;
   int block, grid;
   int nt, half;  // half: 8-byte plane accesses instead of 16
+  size_t lds;    // dynamic LDS per block (caps resident blocks)
   int64_t total_tiles;
   ImgDesc* d_img;
   double* d_partial;
@@ -206,12 +210,13 @@ hipError_t enqueue(const polsar_batch* b, hipStream_t s) {
   do {                                                                                                        \
     constexpr int VW = 16 / sizeof(T);                                                                        \
     const dim3 g(b->grid), t(b->block);                                                                        \
+    const size_t lds = b->lds;                                                                                 \
     if (b->half) {                                                                                            \
-      if (b->nt) hipLaunchKernelGGL((k_batch<T, OPV, true, VW / 2>), g, t, 0, s, b->args);                    \
-      else hipLaunchKernelGGL((k_batch<T, OPV, false, VW / 2>), g, t, 0, s, b->args);                         \
+      if (b->nt) hipLaunchKernelGGL((k_batch<T, OPV, true, VW / 2>), g, t, lds, s, b->args);                  \
+      else hipLaunchKernelGGL((k_batch<T, OPV, false, VW / 2>), g, t, lds, s, b->args);                       \
     } else {                                                                                                  \
-      if (b->nt) hipLaunchKernelGGL((k_batch<T, OPV, true, VW>), g, t, 0, s, b->args);                        \
-      else hipLaunchKernelGGL((k_batch<T, OPV, false, VW>), g, t, 0, s, b->args);                             \
+      if (b->nt) hipLaunchKernelGGL((k_batch<T, OPV, true, VW>), g, t, lds, s, b->args);                      \
+      else hipLaunchKernelGGL((k_batch<T, OPV, false, VW>), g, t, lds, s, b->args);                           \
     }                                                                                                         \
   } while (0)
   if (b->dtype == POLSAR_F32) {
@@ -272,13 +277,11 @@ int polsar_batch_create(const polsar_image* imgs, int count, int dtype, int meth
   if (grad_loss && !aligned(grad_loss, 8)) return POLSAR_E_ALIGN;
   if (counters && !aligned(counters, 8)) return POLSAR_E_ALIGN;
   const size_t es = dtype == POLSAR_F64 ? 8 : 4;
-  // Tile size: that of the per-call Wishart kernel when the batch evaluates
-  // the Wishart term (so per-image losses are summed in the same order),
-  // else that of the per-call inverse kernel.
-  polsar_launch cfg, wcfg;
-  polsar_get_launch(0, dtype, method, precision, &cfg);
-  polsar_get_launch(1, dtype, 0, 0, &wcfg);
-  const polsar_launch& use = (ops & (POLSAR_OP_WISHART_FWD | POLSAR_OP_WISHART_BWD)) ? wcfg : cfg;
+  // Launch shape: the batch entry of the launch table (op 3: block, blocks
+  // per compute unit, access width, non-temporal); a tile is one vector per
+  // lane of one block.
+  polsar_launch use;
+  polsar_get_launch(3, dtype, method, precision, &use);
   const int block = use.block;
   const bool half = use.vector_bytes == 8;
   const int VW = (int)((half ? 8 : 16) / es);
@@ -343,8 +346,9 @@ int polsar_batch_create(const polsar_image* imgs, int count, int dtype, int meth
   b->block = block;
   b->nt = use.nontemporal;
   b->half = half ? 1 : 0;
+  b->lds = polsar_launch_lds_bytes(use, 0);
   b->total_tiles = tiles;
-  const int gpc = grid_per_cu > 0 ? grid_per_cu : 8;
+  const int gpc = grid_per_cu > 0 ? grid_per_cu : use.grid_per_cu;
   b->grid = (int)std::min<int64_t>(tiles, (int64_t)gpc * device_cus_b());
   if (hipMalloc((void**)&b->d_img, sizeof(ImgDesc) * count) != hipSuccess) { release(b); return POLSAR_E_HIP; }
   if (hipMalloc((void**)&b->d_partial, sizeof(double) * tiles) != hipSuccess) { release(b); return POLSAR_E_HIP; }

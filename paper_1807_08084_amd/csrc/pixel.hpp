@@ -70,10 +70,12 @@ PX_HD T det_from_cofactors(const T z[9], const T c[9]) {
 }
 
 // Classify an evaluated pixel: non-finite beats not-positive-definite.
+// Positive definiteness by Sylvester's criterion on the leading principal
+// minors a, f_c = a d - |b|^2 (a cofactor already at hand) and det.
 template <class T>
-PX_HD int classify(T det, T t) {
+PX_HD int classify(T det, T t, T a, T minor2) {
   if (!finite_(det)) return ST_NONFINITE;
-  if (!(det > T(0))) return ST_NOT_PD;
+  if (!(det > T(0)) || !(a > T(0)) || !(minor2 > T(0))) return ST_NOT_PD;
   if (!finite_(t)) return ST_NONFINITE;
   return ST_OK;
 }
@@ -86,7 +88,7 @@ PX_HD int adjugate_plain(const T z[9], T x[9], T& det) {
   const T t = T(1) / det;
 #pragma unroll
   for (int k = 0; k < 9; ++k) x[k] = t * c[k];
-  return classify(det, t);
+  return classify(det, t, z[0], c[2]);
 }
 
 // FP32 storage, FP64 arithmetic: the same formulas on exactly widened inputs.
@@ -99,7 +101,7 @@ PX_HD int adjugate_wide(const float z[9], float x[9], float& det) {
   for (int k = 0; k < 9; ++k) x[k] = (float)xd[k];
   det = (float)dd;
   const float t = 1.0f / det;
-  int st32 = classify(det, t);
+  int st32 = classify(det, t, z[0], 1.0f);  // the minors were checked in FP64
   return st32 > st ? st32 : st;
 }
 
@@ -219,7 +221,7 @@ PX_HD int adjugate_comp(const double z[9], double x[9], double& det) {
   det = det_comp(z, c, mag, bound);
   const double t = 1.0 / det;
   scale_comp(c, t, x);
-  return classify(det, t);
+  return classify(det, t, z[0], c[2].hi + c[2].lo);
 }
 
 // Relative threshold on the determinant bound above which an FP32 pixel is
@@ -240,7 +242,8 @@ PX_HD bool adjugate_comp_try(const float z[9], float x[9], float& det, float* bo
   det = det_comp(z, c, mag, bound);
   if (bound_out) *bound_out = bound;
   const float t = 1.0f / det;
-  const bool ok = det > 0.0f && finite_(det) && finite_(t) && !(bound > REROUTE_REL * det);
+  const bool ok = det > 0.0f && finite_(det) && finite_(t) && !(bound > REROUTE_REL * det) && z[0] > 0.0f &&
+                  c[2].hi + c[2].lo > 0.0f;
   if (ok) scale_comp(c, t, x);
   return ok;
 }
@@ -255,7 +258,7 @@ PX_HD int adjugate_comp_reroute(const float z[9], float x[9], float& det) {
   for (int k = 0; k < 9; ++k) x[k] = (float)xd[k];
   det = (float)dd;
   if (st == ST_OK) {
-    st = classify(det, 1.0f / det);
+    st = classify(det, 1.0f / det, z[0], 1.0f);  // the minors were checked in FP64
     if (st == ST_OK) st = ST_REROUTED;
   }
   return st;
@@ -402,7 +405,7 @@ PX_HD int wishart_pixel(const T s[9], const T z[9], T n_looks, bool want_ell, T&
   cofactors_plain(s, c);
   const T det = det_from_cofactors(s, c);
   const T t = T(1) / det;
-  const int st = classify(det, t);
+  const int st = classify(det, t, s[0], c[2]);
   if (want_ell) {
     const T tr = c[0] * z[0] + c[1] * z[1] + c[2] * z[2] +
                  T(2) * (c[3] * z[3] + c[4] * z[4] + c[5] * z[5] + c[6] * z[6] + c[7] * z[7] + c[8] * z[8]);

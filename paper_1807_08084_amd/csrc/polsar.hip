@@ -485,13 +485,39 @@ std::map<std::tuple<int, int, int, int>, polsar_launch> g_cfg;
 // Defaults from a sweep of all launch shapes on MI355X (4096x4096 image):
 // one 128-lane tile per block, one 128-bit vector per lane per plane,
 // non-temporal (streaming) loads and stores.
+// The Wishart kernel in FP64 with 16-byte accesses needs all 256 VGPRs (one
+// wave per SIMD); with 8-byte accesses it runs at three waves per SIMD and
+// 20% faster.  The batch kernel (op 3) is a persistent grid.  blocks_per_cu
+// caps the resident blocks: with 4-5 waves per CU the 19 concurrent plane
+// streams of a 3x3 inverse reach ~82% of HBM peak, with more they contend.
 polsar_launch default_launch(int op, int dtype, int method, int prec) {
-  (void)dtype;
   (void)method;
   (void)prec;
-  if (op == 1) return polsar_launch{256, 1, 0, 1, 16};
-  if (op == 2) return polsar_launch{128, 1, 0, 1, 16};
-  return polsar_launch{128, 1, 0, 1, 16};
+  if (op == 1) return dtype == POLSAR_F64 ? polsar_launch{256, 1, 0, 1, 8, 0} : polsar_launch{256, 1, 0, 1, 16, 0};
+  if (op == 3) return dtype == POLSAR_F64 ? polsar_launch{256, 1, 8, 1, 16, 0} : polsar_launch{256, 1, 16, 1, 16, 0};
+  return polsar_launch{128, 1, 0, 1, 16, 0};
+}
+
+// Dynamic LDS bytes for a launch: what the kernel needs, raised so that at
+// most blocks_per_cu blocks fit in a compute unit's LDS.
+int lds_per_cu() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 160 << 10;
+  if (!cached[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess || v <= 0)
+      v = 160 << 10;
+    cached[dev] = v;
+  }
+  return cached[dev];
+}
+
+size_t launch_lds(const polsar_launch& c, size_t need) {
+  if (c.blocks_per_cu <= 0) return need;
+  size_t pad = (size_t)lds_per_cu() / (size_t)(c.blocks_per_cu + 1) + 1024;
+  pad = std::min<size_t>(pad, 64 << 10);
+  return std::max(need, pad);
 }
 
 polsar_launch get_cfg(int op, int dtype, int method, int prec) {
@@ -503,10 +529,12 @@ polsar_launch get_cfg(int op, int dtype, int method, int prec) {
 bool valid_launch(const polsar_launch& c, int op) {
   if (c.block != 64 && c.block != 128 && c.block != 256) return false;
   if (c.unroll != 1 && c.unroll != 2 && !(op == 0 && c.unroll == 4)) return false;
-  if (op == 2 && c.unroll != 1) return false;
+  if ((op == 2 || op == 3) && c.unroll != 1) return false;
+  if (op == 3 && c.grid_per_cu == 0) return false;
   if (c.grid_per_cu < 0 || c.grid_per_cu > 64) return false;
   if (c.nontemporal != 0 && c.nontemporal != 1) return false;
   if (c.vector_bytes != 16 && c.vector_bytes != 8) return false;
+  if (c.blocks_per_cu < 0 || c.blocks_per_cu > 64) return false;
   return true;
 }
 
@@ -553,7 +581,7 @@ int op_code(int method, int prec) {
 // Launch helpers: pick the template instance for (V, U, NT).
 template <class T, int OP, int V, int U>
 hipError_t go_inv_det(const polsar_launch& c, int64_t grid, InvDetArgs& a, hipStream_t s) {
-  const size_t lds = (OP == ADJ_COMP && std::is_same<T, float>::value) ? comp_queue_bytes(c.block, V) : 0;
+  const size_t lds = launch_lds(c, (OP == ADJ_COMP && std::is_same<T, float>::value) ? comp_queue_bytes(c.block, V) : 0);
   if (c.nontemporal)
     hipLaunchKernelGGL((k_inv_det<T, OP, V, U, true>), dim3((unsigned)grid), dim3(c.block), lds, s, a);
   else
@@ -663,10 +691,11 @@ hipError_t dispatch_multilook_v(const polsar_launch& c, MultilookArgs& a, hipStr
   a.o.tiles = std::max<int64_t>(1, (a.o.nvec + c.block - 1) / c.block);
   int64_t grid = a.o.tiles;
   if (c.grid_per_cu > 0) grid = std::min<int64_t>(grid, (int64_t)c.grid_per_cu * device_cus());
+  const size_t lds = launch_lds(c, 0);
   if (c.nontemporal)
-    hipLaunchKernelGGL((k_multilook<T, OP, V, true>), dim3((unsigned)grid), dim3(c.block), 0, s, a);
+    hipLaunchKernelGGL((k_multilook<T, OP, V, true>), dim3((unsigned)grid), dim3(c.block), lds, s, a);
   else
-    hipLaunchKernelGGL((k_multilook<T, OP, V, false>), dim3((unsigned)grid), dim3(c.block), 0, s, a);
+    hipLaunchKernelGGL((k_multilook<T, OP, V, false>), dim3((unsigned)grid), dim3(c.block), lds, s, a);
   return hipGetLastError();
 }
 
@@ -703,10 +732,11 @@ hipError_t dispatch_block_v(const polsar_launch& c, BlockArgs& a, hipStream_t s)
   a.o.tiles = std::max<int64_t>(1, (a.o.nvec + c.block - 1) / c.block);
   int64_t grid = a.o.tiles;
   if (c.grid_per_cu > 0) grid = std::min<int64_t>(grid, (int64_t)c.grid_per_cu * device_cus());
+  const size_t lds = launch_lds(c, 0);
   if (c.nontemporal)
-    hipLaunchKernelGGL((k_blockdiag<T, OP, V, true>), dim3((unsigned)grid), dim3(c.block), 0, s, a);
+    hipLaunchKernelGGL((k_blockdiag<T, OP, V, true>), dim3((unsigned)grid), dim3(c.block), lds, s, a);
   else
-    hipLaunchKernelGGL((k_blockdiag<T, OP, V, false>), dim3((unsigned)grid), dim3(c.block), 0, s, a);
+    hipLaunchKernelGGL((k_blockdiag<T, OP, V, false>), dim3((unsigned)grid), dim3(c.block), lds, s, a);
   return hipGetLastError();
 }
 
@@ -737,10 +767,11 @@ hipError_t launch_block(int dtype, int op, const polsar_launch& c, bool vec, Blo
 // ---- Wishart launch
 template <class T, int V, int U>
 hipError_t go_wishart(const polsar_launch& c, int64_t grid, WishartArgs& a, hipStream_t s) {
+  const size_t lds = launch_lds(c, 0);
   if (c.nontemporal)
-    hipLaunchKernelGGL((k_wishart<T, V, U, true>), dim3((unsigned)grid), dim3(c.block), 0, s, a);
+    hipLaunchKernelGGL((k_wishart<T, V, U, true>), dim3((unsigned)grid), dim3(c.block), lds, s, a);
   else
-    hipLaunchKernelGGL((k_wishart<T, V, U, false>), dim3((unsigned)grid), dim3(c.block), 0, s, a);
+    hipLaunchKernelGGL((k_wishart<T, V, U, false>), dim3((unsigned)grid), dim3(c.block), lds, s, a);
   return hipGetLastError();
 }
 
@@ -769,6 +800,9 @@ int64_t max_wishart_tiles(int dtype, int64_t n) {
 }
 
 }  // namespace
+
+// LDS bytes of a launch with this shape (shared with the batch kernel).
+size_t polsar_launch_lds_bytes(const polsar_launch& c, size_t need) { return launch_lds(c, need); }
 
 // ============================================================== C ABI
 struct polsar_batch;  // defined in batch.hip
@@ -804,13 +838,13 @@ int polsar_device_compute_units(int* cus) {
 }
 
 int polsar_get_launch(int op, int dtype, int method, int precision, polsar_launch* out) {
-  if (!out || op < 0 || op > 2) return POLSAR_E_ARG;
+  if (!out || op < 0 || op > 3) return POLSAR_E_ARG;
   *out = get_cfg(op, dtype, method, precision);
   return POLSAR_OK;
 }
 
 int polsar_set_launch(int op, int dtype, int method, int precision, const polsar_launch* cfg) {
-  if (!cfg || op < 0 || op > 2 || !valid_launch(*cfg, op)) return POLSAR_E_ARG;
+  if (!cfg || op < 0 || op > 3 || !valid_launch(*cfg, op)) return POLSAR_E_ARG;
   std::lock_guard<std::mutex> g(g_mu);
   g_cfg[std::make_tuple(op, dtype, method, precision)] = *cfg;
   return POLSAR_OK;
@@ -977,15 +1011,17 @@ int polsar_autotune_inv_det(int dtype, int method, int precision, int64_t n, con
     return POLSAR_E_HIP;
   }
   const int op = op_code(method, precision);
-  polsar_launch win{0, 0, 0, 0, 0};
+  polsar_launch win{0, 0, 0, 0, 0, 0};
   float win_ms = 1e30f;
   int rc = POLSAR_OK;
+  // candidates: block x unroll x {one tile per block, 8 blocks per CU
+  // persistent} x access width x resident-block cap; streaming accesses
   for (int block : {64, 128, 256})
-    for (int unroll : {1, 2, 4})
-      for (int gpc : {0, 2, 4, 8})
-        for (int nt : {0, 1})
-          for (int vb : {16, 8}) {
-          polsar_launch c{block, unroll, gpc, nt, vb};
+    for (int unroll : {1, 2})
+      for (int gpc : {0, 8})
+        for (int vb : {16, 8})
+          for (int bpc : {0, 2, 3, 4, 5, 6, 8}) {
+          polsar_launch c{block, unroll, gpc, 1, vb, bpc};
           InvDetArgs aa = a;
           if (launch_inv_det(dtype, op, c, vec, aa, s) != hipSuccess) { rc = POLSAR_E_HIP; goto done; }
           (void)hipEventRecord(e0, s);

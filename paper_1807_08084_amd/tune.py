@@ -16,7 +16,7 @@ import torch
 
 from . import ops
 
-OPS = {"inv_det": 0, "wishart": 1}
+OPS = {"inv_det": 0, "wishart": 1, "multilook": 2, "batch": 3}
 
 
 def _time(fn, reps: int) -> float:
@@ -35,9 +35,12 @@ def tune_inv_det(z: torch.Tensor, method: str, precision: str, reps: int = 10):
     return ops.autotune_inv_det(z, method, precision, reps=reps)
 
 
+BPC = (0, 2, 3, 4, 5, 6, 8)  # resident-block caps tried
+
+
 def wishart_candidates():
-    for b, u, g, nt, vb in itertools.product((64, 128, 256), (1, 2), (0, 4, 8), (0, 1), (16, 8)):
-        yield dict(block=b, unroll=u, grid_per_cu=g, nontemporal=nt, vector_bytes=vb)
+    for b, u, g, vb, bpc in itertools.product((64, 128, 256), (1, 2), (0, 8), (16, 8), BPC):
+        yield dict(block=b, unroll=u, grid_per_cu=g, nontemporal=1, vector_bytes=vb, blocks_per_cu=bpc)
 
 
 def tune_wishart(sigma: torch.Tensor, z: torch.Tensor, n_looks: float, reps: int = 10):
@@ -51,6 +54,39 @@ def tune_wishart(sigma: torch.Tensor, z: torch.Tensor, n_looks: float, reps: int
         if ms < best_ms:
             best, best_ms = cfg, ms
     ops.set_launch(1, sigma.dtype, "adjugate", "plain", best)
+    return best, best_ms
+
+
+def tune_multilook(looks: torch.Tensor, n_looks: int, method: str = "adjugate", precision: str = "compensated",
+                   reps: int = 10):
+    best, best_ms = None, float("inf")
+    for b, g, vb, bpc in itertools.product((64, 128, 256), (0, 8), (16, 8), BPC):
+        cfg = dict(block=b, unroll=1, grid_per_cu=g, nontemporal=1, vector_bytes=vb, blocks_per_cu=bpc)
+        ops.set_launch(2, looks.dtype, method, precision, cfg)
+        ms = _time(lambda: ops.multilook_inv_det(looks, n_looks, method, precision), reps)
+        if ms < best_ms:
+            best, best_ms = cfg, ms
+    ops.set_launch(2, looks.dtype, method, precision, best)
+    return best, best_ms
+
+
+def tune_batch(items, method: str = "adjugate", precision: str = "compensated", reps: int = 5):
+    """Sweep the batch launch (block, blocks per CU, access width); each
+    candidate builds its own plan (and graph)."""
+    from .batch import BatchPlan
+    dtype = items[0]["z"].dtype
+    best, best_ms = None, float("inf")
+    for b, g, vb, bpc in itertools.product((64, 128, 256), (2, 4, 8, 16), (16, 8), (0, 2, 4, 6)):
+        if bpc and g > bpc:
+            continue  # a persistent grid larger than what can be resident
+        cfg = dict(block=b, unroll=1, grid_per_cu=g, nontemporal=1, vector_bytes=vb, blocks_per_cu=bpc)
+        ops.set_launch(3, dtype, method, precision, cfg)
+        plan = BatchPlan(items, method, precision, status=False)
+        ms = _time(plan.run, reps)
+        plan.close()
+        if ms < best_ms:
+            best, best_ms = cfg, ms
+    ops.set_launch(3, dtype, method, precision, best)
     return best, best_ms
 
 

@@ -121,6 +121,8 @@ def _edge_planes():
     add(np.inf, 1, 1)
     add(1, 1, 1, e=np.inf + 0j)
     add(4, 5, 6, 1 + 1j, 2j, 1 - 1j)   # the worked example
+    add(0, 0, 0, 1 + 0j, 1 + 0j, 1 + 0j)  # eigenvalues (2, -1, -1): det 2 > 0, a = 0
+    add(1, 1, -1, 2 + 0j)              # eigenvalues (3, -1, -1): det 3 > 0, a > 0, ad - |b|^2 < 0
     return np.array(cols, dtype=np.float64).T
 
 
@@ -134,6 +136,8 @@ def test_edge_cases(ops, dtype, method, prec):
     assert st[3] == 2 and st[4] == 2 and st[5] == 2
     assert st[6] == 3 and st[7] == 3 and st[8] == 3
     assert st[9] == 0
+    assert st[10] == 2 and st[11] == 2          # indefinite with a positive determinant
+    assert det[10] > 0 and det[11] > 0
     want = np.array([28, 20, 18, -8, -4, 2, -10, -2, 6]) / 80.0
     u = U64 if dtype == torch.float64 else U32
     assert np.allclose(inv[:, 9], want, rtol=16 * u, atol=16 * u) and abs(det[9] - 80) <= 80 * 16 * u
@@ -186,7 +190,11 @@ def test_results_independent_of_launch(ops, small):
         for cfg in ({"block": 64, "unroll": 1, "grid_per_cu": 0, "nontemporal": 0, "vector_bytes": 16},
                     {"block": 256, "unroll": 4, "grid_per_cu": 2, "nontemporal": 1, "vector_bytes": 16},
                     {"block": 128, "unroll": 2, "grid_per_cu": 8, "nontemporal": 1, "vector_bytes": 8},
-                    {"block": 64, "unroll": 4, "grid_per_cu": 0, "nontemporal": 0, "vector_bytes": 8}):
+                    {"block": 64, "unroll": 4, "grid_per_cu": 0, "nontemporal": 0, "vector_bytes": 8},
+                    {"block": 64, "unroll": 1, "grid_per_cu": 0, "nontemporal": 1, "vector_bytes": 16,
+                     "blocks_per_cu": 4},
+                    {"block": 256, "unroll": 2, "grid_per_cu": 8, "nontemporal": 1, "vector_bytes": 16,
+                     "blocks_per_cu": 2}):
             ops.set_launch(0, torch.float32, "adjugate", "compensated", cfg)
             inv, det, st = ops.inv_det(z, "adjugate", "compensated", status=True)
             outs.append((inv.clone(), det.clone(), st.clone()))

@@ -64,3 +64,18 @@ def test_f32_compensated_reroute_and_bound():
     assert np.mean(st[(k > 1e6) & pd] == 1) > 0.5
     # every oracle-PD pixel comes out positive definite (kept or fixed by FP64)
     assert np.all(st[pd & (k < 1e7)] <= 1)
+
+
+def test_indefinite_with_positive_determinant_is_not_pd():
+    """Eigenvalues (-l1, -l2, l3): det > 0 but not positive definite; the
+    leading-minor test flags every one (the oracle's pivot signs agree)."""
+    rng = np.random.default_rng(33)
+    m = 5000
+    eig = np.stack([-10.0 ** -rng.uniform(0, 3, m), -10.0 ** -rng.uniform(0, 3, m), 10.0 ** -rng.uniform(0, 3, m)], 1)
+    U = synth.haar_unitary(rng, m)
+    z = synth.pack(np.einsum("mij,mj,mkj->mik", U, eig, np.conj(U)))
+    assert np.all(oracle.pd_class(z) == 2)
+    _, det64, st64 = pixel.adjugate_comp_f64(z)
+    assert np.all(det64 > 0) and np.all(st64 == 2)
+    _, det32, st32, _ = pixel.adjugate_comp_f32(z.astype(np.float32))
+    assert np.all(st32 == 2)
