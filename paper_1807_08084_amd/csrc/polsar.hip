@@ -491,11 +491,24 @@ std::map<std::tuple<int, int, int, int>, polsar_launch> g_cfg;
 // caps the resident blocks: with 4-5 waves per CU the 19 concurrent plane
 // streams of a 3x3 inverse reach ~82% of HBM peak, with more they contend.
 polsar_launch default_launch(int op, int dtype, int method, int prec) {
-  (void)method;
-  (void)prec;
-  if (op == 1) return dtype == POLSAR_F64 ? polsar_launch{256, 1, 0, 1, 8, 0} : polsar_launch{256, 1, 0, 1, 16, 0};
-  if (op == 3) return dtype == POLSAR_F64 ? polsar_launch{256, 1, 8, 1, 16, 0} : polsar_launch{256, 1, 16, 1, 16, 0};
-  return polsar_launch{128, 1, 0, 1, 16, 0};
+  const bool f64 = dtype == POLSAR_F64, chol = method == POLSAR_CHOLESKY;
+  switch (op) {
+    case 1:
+      return f64 ? polsar_launch{256, 1, 0, 1, 8, 0} : polsar_launch{256, 1, 0, 1, 16, 0};
+    case 2:
+      return f64 ? polsar_launch{256, 1, 0, 1, 8, 4} : polsar_launch{128, 1, 0, 1, 16, 0};
+    case 3:
+      return f64 ? polsar_launch{256, 1, 2, 1, 16, 6} : polsar_launch{256, 1, 16, 1, 16, 0};
+    default:
+      break;
+  }
+  // op 0: winners of the autotuner on a 4096x4096 image
+  if (!chol && prec == POLSAR_COMPENSATED) return f64 ? polsar_launch{256, 1, 0, 1, 8, 3} : polsar_launch{128, 1, 0, 1, 16, 4};
+  if (chol && prec == POLSAR_PLAIN) return f64 ? polsar_launch{64, 1, 0, 1, 16, 5} : polsar_launch{256, 1, 0, 1, 8, 3};
+  if (!chol && prec == POLSAR_PLAIN) return f64 ? polsar_launch{128, 1, 0, 1, 8, 0} : polsar_launch{256, 1, 0, 1, 8, 0};
+  if (chol && prec == POLSAR_WIDE) return polsar_launch{64, 2, 0, 1, 16, 0};
+  if (chol) return polsar_launch{64, 1, 0, 1, 16, 0};
+  return polsar_launch{128, 1, 0, 1, 8, 0};  // adjugate, FP32 storage with FP64 arithmetic
 }
 
 // Dynamic LDS bytes for a launch: what the kernel needs, raised so that at

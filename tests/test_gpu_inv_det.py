@@ -137,7 +137,8 @@ def test_edge_cases(ops, dtype, method, prec):
     assert st[6] == 3 and st[7] == 3 and st[8] == 3
     assert st[9] == 0
     assert st[10] == 2 and st[11] == 2          # indefinite with a positive determinant
-    assert det[10] > 0 and det[11] > 0
+    if method == "adjugate":
+        assert det[10] > 0 and det[11] > 0      # (Cholesky meets a negative pivot: NaN)
     want = np.array([28, 20, 18, -8, -4, 2, -10, -2, 6]) / 80.0
     u = U64 if dtype == torch.float64 else U32
     assert np.allclose(inv[:, 9], want, rtol=16 * u, atol=16 * u) and abs(det[9] - 80) <= 80 * 16 * u
