@@ -279,6 +279,15 @@ def main():
                          "frac_hbm": round(mb / (m_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                          "bytes_per_px": mb // n_px}
         del lk
+        # nonlocal-means filter, 23x23 window, on the inverse / det just computed
+        zimg = z32.view(9, 4096, 4096)
+        inv_img, det_img = inv.view(9, 4096, 4096), det.view(4096, 4096).contiguous()
+        for dist, aux in (("kl", inv_img), ("bhattacharyya", det_img)):
+            f = (lambda dist=dist, aux=aux: ops.nlm_wishart(zimg, aux, 4.0, 11, 16.0, dist))
+            n_ms = time_calls(f, 5, 1, torch)
+            rows[f"nlm_{dist}_r11_f32"] = {"gpx_s": round(n_px / n_ms / 1e6, 4), "ms": round(n_ms, 3),
+                                           "pairs_per_s": float(f"{n_px * 529 / (n_ms * 1e-3):.4g}"),
+                                           "window": "23x23"}
         # host-resident image through the out-of-core streamer (PCIe included)
         zh = torch.empty((9, n_px), dtype=torch.float32, pin_memory=True)
         zh.copy_(torch.from_numpy(z64.astype(np.float32)))

@@ -123,6 +123,26 @@ int polsar_blockdiag_inv_det(int dtype, int method, int precision, int64_t n, in
                              void* det, void* block_det, int64_t block_det_pitch,
                              uint8_t* status, unsigned long long* counters, void* stream);
 
+/* Nonlocal-means filtering with stochastic distances between Wishart laws
+ * (the use the Introduction gives for fast inverses and determinants: every
+ * pixel is compared with each pixel of a (2r+1) x (2r+1) search window).
+ *   out_p = sum_q w_pq Z_q / sum_q w_pq,  w_pq = exp(-d(Z_p, Z_q) / h),
+ *   KL:            d = N/2 (tr(Z_p^-1 Z_q) + tr(Z_q^-1 Z_p)) - 3N
+ *   BHATTACHARYYA: d = N (ln det((Z_p + Z_q)/2) - (ln det Z_p + ln det Z_q)/2)
+ * The window is clipped at the image border.  Image: height x width pixels,
+ * row-major within each plane.
+ *   z     in: 9 planes of Z (pitch z_pitch)
+ *   aux   in: KL: the 9 planes of Z^-1; BHATTACHARYYA: the det plane (both as
+ *         polsar_inv_det returns them)
+ *   out   out: 9 planes of the filtered covariance (pitch out_pitch)
+ *   wsum  out (nullable): sum of the weights per pixel
+ * radius <= 16, n_looks > 0, h > 0.  Outputs must not overlap inputs. */
+enum { POLSAR_DIST_KL = 0, POLSAR_DIST_BHATTACHARYYA = 1 };
+int polsar_nlm_wishart(int dtype, int distance, int64_t height, int64_t width, int radius,
+                       double n_looks, double h, const void* z, int64_t z_pitch,
+                       const void* aux, int64_t aux_pitch, void* out, int64_t out_pitch,
+                       void* wsum, void* stream);
+
 typedef enum { POLSAR_FWD = 1, POLSAR_BWD = 2, POLSAR_FWD_BWD = 3 } polsar_pass;
 
 /* Wishart log-likelihood term, summed over pixels:

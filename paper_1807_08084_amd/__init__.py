@@ -12,7 +12,7 @@ __all__ = ["inv_det", "multilook_inv_det", "wishart_loglik", "wishart_nll", "Wis
 
 def __getattr__(name):
     # the binding (and torch) load on first use, so the generator stays light
-    if name in ("inv_det", "multilook_inv_det", "blockdiag_inv_det", "Streamer", "upload_planes", "empty_planes", "recommended_pitch",
+    if name in ("inv_det", "multilook_inv_det", "blockdiag_inv_det", "Streamer", "nlm_wishart", "upload_planes", "empty_planes", "recommended_pitch",
                 "wishart_loglik", "wishart_nll", "WishartNLL", "autotune_inv_det",
                 "get_launch", "set_launch", "stream_copy", "compute_units", "workspace_bytes"):
         from . import ops

@@ -64,6 +64,7 @@ def lib():
         L.polsar_streamer_run.argtypes = [vp, i64, vp, i64, vp, i64, vp, vp, vp]
         L.polsar_streamer_destroy.argtypes = [vp]
         L.polsar_streamer_destroy.restype = None
+        L.polsar_nlm_wishart.argtypes = [i, i, i64, i64, i, d, d, vp, i64, vp, i64, vp, i64, vp, vp]
         L.polsar_wishart_loglik.argtypes = [i, i, i64, vp, i64, vp, i64, d, vp, vp, vp, vp, i64, vp, sz, vp, vp]
         L.polsar_wishart_workspace_bytes.argtypes = [i, i64]
         L.polsar_wishart_workspace_bytes.restype = sz

@@ -1,0 +1,185 @@
+// Nonlocal-means filtering of a PolSAR covariance image with stochastic
+// distances between Wishart laws, the consumer the Introduction motivates:
+// every pixel compares its covariance with each pixel of a (2r+1)^2 search
+// window, which needs the inverse (symmetrized Kullback-Leibler distance) or
+// the determinant (Bhattacharyya distance) of every covariance, and the
+// filtered covariance is the weighted mean
+//     out_p = sum_q w_pq Z_q / sum_q w_pq,   w_pq = exp(-d(Z_p, Z_q) / h).
+// Distances for N looks (the Sigma-free terms cancel):
+//   KL: d = N/2 (tr(Z_p^-1 Z_q) + tr(Z_q^-1 Z_p)) - 3N
+//   B:  d = N (ln det((Z_p + Z_q)/2) - (ln det Z_p + ln det Z_q)/2)
+// with tr(AB) = a_A a_B + d_A d_B + f_A f_B + 2 (Re/Im products of b, c, e)
+// for Hermitian A, B, and det of the pair mean by the row-0 real-part
+// expansion (Eq. detr).  Windows are clipped at the image border.
+//
+// Blocks cover TW x TH output pixels.  For each window row offset dy the
+// block stages the band of TH rows x (TW + 2r) columns it needs (covariance
+// and inverse or log2 det, structure of arrays in LDS), then every lane
+// sweeps its 2r+1 horizontal neighbours in that band.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "../../include/polsar.h"
+#include "pixel.hpp"
+
+namespace {
+
+constexpr int TW = 64, TH = 4, MAX_R = 16;
+
+struct NlmArgs {
+  const void* z;
+  int64_t zp;
+  const void* aux;  // KL: 9 inverse planes; B: det plane
+  int64_t ap;
+  void* out;
+  int64_t op;
+  void* wsum;
+  int64_t H, W;
+  int r;
+  double n_looks, h;
+};
+
+template <class T> __device__ __forceinline__ T exp2_(T x);
+template <> __device__ __forceinline__ float exp2_(float x) { return exp2f(x); }
+template <> __device__ __forceinline__ double exp2_(double x) { return exp2(x); }
+template <class T> __device__ __forceinline__ T log2_(T x);
+template <> __device__ __forceinline__ float log2_(float x) { return log2f(x); }
+template <> __device__ __forceinline__ double log2_(double x) { return log2(x); }
+
+// DIST 0: symmetrized Kullback-Leibler (F = 18 staged values per pixel:
+// Z and Z^-1); DIST 1: Bhattacharyya (F = 10: Z and log2 det Z).
+template <class T, int DIST>
+__global__ __launch_bounds__(TW * TH) void k_nlm(NlmArgs a) {
+  constexpr int F = DIST == 0 ? 18 : 10;
+  constexpr int BW = TW + 2 * MAX_R;
+  __shared__ T band[F][TH][BW];
+  const T* __restrict__ Z = (const T*)a.z;
+  const T* __restrict__ A = (const T*)a.aux;
+  const int tx = threadIdx.x % TW, ty = threadIdx.x / TW;
+  const int64_t x0 = (int64_t)blockIdx.x * TW, y0 = (int64_t)blockIdx.y * TH;
+  const int64_t px = x0 + tx, py = y0 + ty;
+  const bool valid = px < a.W && py < a.H;
+  const int r = a.r, bw = TW + 2 * r;
+  const T N = (T)a.n_looks;
+  const T log2e = (T)1.4426950408889634;
+  // this lane's pixel: Z_p with the off-diagonal doubled (for tr(Q^-1 P)),
+  // and Z_p^-1 with the off-diagonal doubled, or log2 det Z_p
+  T zp2[9], ip2[9], lp = 0;
+  if (valid) {
+    const int64_t i = py * a.W + px;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) zp2[k] = Z[k * a.zp + i] * (k < 3 ? T(1) : T(2));
+    if (DIST == 0) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) ip2[k] = A[k * a.ap + i] * (k < 3 ? T(1) : T(2));
+    } else {
+      lp = log2_(A[i]);
+    }
+  }
+  T acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  T wsum = 0;
+  // w = exp2(alpha * s + beta): KL s = t1 + t2; B s = log2 det(Zp + Zq) - (lp + lq)/2
+  const T alpha = DIST == 0 ? -N * log2e / (T(2) * (T)a.h) : -N / (T)a.h;
+  const T beta = DIST == 0 ? T(3) * N * log2e / (T)a.h : T(3) * N / (T)a.h;
+  for (int dy = -r; dy <= r; ++dy) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < TH * bw; idx += TW * TH) {
+      const int row = idx / bw, col = idx % bw;
+      const int64_t gy = y0 + row + dy, gx = x0 - r + col;
+      if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
+        const int64_t i = gy * a.W + gx;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) band[k][row][col] = Z[k * a.zp + i];
+        if (DIST == 0) {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) band[9 + k][row][col] = A[k * a.ap + i];
+        } else {
+          band[9][row][col] = log2_(A[i]);
+        }
+      }
+    }
+    __syncthreads();
+    const int64_t qy = py + dy;
+    if (!valid || qy < 0 || qy >= a.H) continue;
+    const int lo = px >= r ? -r : (int)-px;
+    const int hi = a.W - 1 - px >= r ? r : (int)(a.W - 1 - px);
+    for (int dx = lo; dx <= hi; ++dx) {
+      const int c = tx + dx + r;
+      T q[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) q[k] = band[k][ty][c];
+      T s;
+      if (DIST == 0) {
+        T t = T(0);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) t += ip2[k] * q[k] + band[9 + k][ty][c] * zp2[k];
+        s = t;
+      } else {
+        // det(Z_p + Z_q): the off-diagonal of zp2 is doubled, halve it back
+        T m[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) m[k] = zp2[k] * (k < 3 ? T(1) : T(0.5)) + q[k];
+        T cf[9];
+        px::cofactors_plain(m, cf);
+        s = log2_(px::det_from_cofactors(m, cf)) - T(0.5) * (lp + band[9][ty][c]);
+      }
+      const T w = exp2_(alpha * s + beta);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) acc[k] += w * q[k];
+      wsum += w;
+    }
+  }
+  if (valid) {
+    const int64_t i = py * a.W + px;
+    const T inv = T(1) / wsum;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) ((T*)a.out)[k * a.op + i] = acc[k] * inv;
+    if (a.wsum) ((T*)a.wsum)[i] = wsum;
+  }
+}
+
+}  // namespace
+
+extern "C" int polsar_nlm_wishart(int dtype, int distance, int64_t height, int64_t width, int radius,
+                                  double n_looks, double h, const void* z, int64_t z_pitch, const void* aux,
+                                  int64_t aux_pitch, void* out, int64_t out_pitch, void* wsum, void* stream) {
+  if (dtype != POLSAR_F32 && dtype != POLSAR_F64) return POLSAR_E_ARG;
+  if (distance != POLSAR_DIST_KL && distance != POLSAR_DIST_BHATTACHARYYA) return POLSAR_E_ARG;
+  if (height < 0 || width < 0 || radius < 0 || radius > MAX_R || !(n_looks > 0.0) || !(h > 0.0))
+    return POLSAR_E_ARG;
+  if (height > (1 << 20) || width > (1 << 20)) return POLSAR_E_ARG;
+  const int64_t n = height * width;
+  const size_t es = dtype == POLSAR_F64 ? 8 : 4;
+  const int aux_planes = distance == POLSAR_DIST_KL ? 9 : 1;
+  if (n == 0) return POLSAR_OK;
+  if (!z || !aux || !out) return POLSAR_E_ARG;
+  if (z_pitch < n || out_pitch < n || (aux_planes > 1 && aux_pitch < n)) return POLSAR_E_ARG;
+  if ((uintptr_t)z % es || (uintptr_t)aux % es || (uintptr_t)out % es || (wsum && (uintptr_t)wsum % es))
+    return POLSAR_E_ALIGN;
+  auto lo_hi = [&](const void* p, int planes, int64_t pitch) {
+    const uintptr_t lo = (uintptr_t)p;
+    return std::make_pair(lo, lo + (uintptr_t)(((planes - 1) * pitch + n) * (int64_t)es));
+  };
+  auto ov = [](std::pair<uintptr_t, uintptr_t> x, std::pair<uintptr_t, uintptr_t> y) {
+    return x.first < y.second && y.first < x.second;
+  };
+  const auto ro = lo_hi(out, 9, out_pitch);
+  if (ov(ro, lo_hi(z, 9, z_pitch)) || ov(ro, lo_hi(aux, aux_planes, aux_pitch))) return POLSAR_E_ALIAS;
+  if (wsum) {
+    const auto rw = lo_hi(wsum, 1, n);
+    if (ov(rw, ro) || ov(rw, lo_hi(z, 9, z_pitch)) || ov(rw, lo_hi(aux, aux_planes, aux_pitch)))
+      return POLSAR_E_ALIAS;
+  }
+  NlmArgs a{z, z_pitch, aux, aux_pitch, out, out_pitch, wsum, height, width, radius, n_looks, h};
+  const dim3 grid((unsigned)((width + TW - 1) / TW), (unsigned)((height + TH - 1) / TH));
+  hipStream_t s = (hipStream_t)stream;
+  if (dtype == POLSAR_F32) {
+    if (distance == POLSAR_DIST_KL) hipLaunchKernelGGL((k_nlm<float, 0>), grid, dim3(TW * TH), 0, s, a);
+    else hipLaunchKernelGGL((k_nlm<float, 1>), grid, dim3(TW * TH), 0, s, a);
+  } else {
+    if (distance == POLSAR_DIST_KL) hipLaunchKernelGGL((k_nlm<double, 0>), grid, dim3(TW * TH), 0, s, a);
+    else hipLaunchKernelGGL((k_nlm<double, 1>), grid, dim3(TW * TH), 0, s, a);
+  }
+  return hipGetLastError() == hipSuccess ? POLSAR_OK : POLSAR_E_HIP;
+}

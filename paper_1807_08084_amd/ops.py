@@ -190,6 +190,37 @@ class Streamer:
             pass
 
 
+_DIST = {"kl": 0, "bhattacharyya": 1}
+
+
+def nlm_wishart(z: torch.Tensor, aux: torch.Tensor, n_looks: float, radius: int, h: float,
+                distance: str = "kl", want_wsum: bool = False, stream=None):
+    """Nonlocal-means filter of a (9, H, W) covariance image with Wishart
+    stochastic distances over a (2r+1)^2 window.  aux: the (9, H, W) inverse
+    planes for "kl", the (H, W) determinant plane for "bhattacharyya" (as
+    inv_det returns them).  Returns (out (9, H, W), wsum (H, W) or None)."""
+    dt = _dtype_code(z)
+    if z.dim() != 3 or z.shape[0] != 9 or not z.is_cuda or not z[0].is_contiguous():
+        raise ValueError("z must be GPU planes of shape (9, H, W), each plane contiguous")
+    H, W = z.shape[1], z.shape[2]
+    if distance == "kl":
+        if aux.shape != z.shape or not aux[0].is_contiguous():
+            raise ValueError("aux must be the (9, H, W) inverse planes")
+        ap = aux.stride(0)
+    else:
+        if aux.shape != z.shape[1:] or not aux.is_contiguous():
+            raise ValueError("aux must be the (H, W) determinant plane")
+        ap = 0
+    if aux.dtype != z.dtype:
+        raise TypeError("aux must have z's dtype")
+    out = empty_planes(9, (H, W), z.dtype, z.device)
+    ws = torch.empty((H, W), dtype=z.dtype, device=z.device) if want_wsum else None
+    rc = L.lib().polsar_nlm_wishart(dt, _DIST[distance], H, W, int(radius), float(n_looks), float(h), _ptr(z),
+                                    z.stride(0), _ptr(aux), ap, _ptr(out), out.stride(0), _ptr(ws), _stream(stream))
+    L.check(rc, "polsar_nlm_wishart")
+    return out, ws
+
+
 def workspace_bytes(dtype: torch.dtype, n: int) -> int:
     return int(L.lib().polsar_wishart_workspace_bytes(L.F32 if dtype == torch.float32 else L.F64, n))
 

@@ -321,3 +321,39 @@ def test_multilook_oracle():
     for i in range(0, 200, 20):
         _, det = exact.inv_det(exact.unpack([int(v) for v in z1[:, i]]))
         assert det == exact.Q(0)
+
+
+# --------------------------------------------------------------- nonlocal means
+def test_nlm_oracle_closed_forms():
+    from oracle import nlm
+    rng = np.random.default_rng(22)
+    z, _ = random_hpd(rng, 1, 1.0)
+    Zf = oracle.full_from_planes(z)
+    N = 4.0
+    for alpha in (0.5, 2.0, 3.0):
+        dkl = nlm.distances(Zf, alpha * Zf, N, "kl")[0]
+        assert abs(dkl - 1.5 * N * (alpha + 1 / alpha - 2)) <= 1e-12 * N
+        db = nlm.distances(Zf, alpha * Zf, N, "bhattacharyya")[0]
+        assert abs(db - N * (3 * math.log((1 + alpha) / 2) - 1.5 * math.log(alpha))) <= 1e-12 * N
+    # d(S, S) = 0 and symmetry on random pairs
+    za, _ = random_hpd(rng, 200, 2.0)
+    zb, _ = random_hpd(rng, 200, 2.0)
+    A, B = oracle.full_from_planes(za), oracle.full_from_planes(zb)
+    for dist in ("kl", "bhattacharyya"):
+        assert np.allclose(nlm.distances(A, A, N, dist), 0, atol=1e-11)
+        assert np.allclose(nlm.distances(A, B, N, dist), nlm.distances(B, A, N, dist), rtol=1e-12)
+        assert np.all(nlm.distances(A, B, N, dist) >= -1e-11)
+    # a uniform image is left unchanged, each weight 1
+    H, W, r = 9, 7, 2
+    zu = np.repeat(z, H * W, axis=1)
+    out, ws = nlm.nlm_wishart(zu, H, W, r, N, 5.0, "kl")
+    assert np.allclose(out, zu, rtol=1e-13)
+    cnt = np.array([[(min(H, y + r + 1) - max(0, y - r)) * (min(W, x + r + 1) - max(0, x - r))
+                     for x in range(W)] for y in range(H)]).ravel()
+    assert np.allclose(ws, cnt, rtol=1e-13)
+    # a huge h gives the box mean over the clipped window
+    img = synth.make_image(8, 6, 4, (2, 2), (1e-2, 1.0), 1).planes.reshape(9, -1)
+    out, _ = nlm.nlm_wishart(img, 8, 6, 1, N, 1e12, "bhattacharyya")
+    P = img.reshape(9, 8, 6)
+    y, x = 3, 2
+    assert np.allclose(out.reshape(9, 8, 6)[:, y, x], P[:, y - 1:y + 2, x - 1:x + 2].mean(axis=(1, 2)), rtol=1e-9)
