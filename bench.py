@@ -219,7 +219,8 @@ def main():
     value = n_px / (ms * 1e-3) / 1e9
     achieved = BYTES_PER_PX["f32"] * n_px / (ms * 1e-3) / 1e9
     kname = "k_inv_det<float, ADJ_COMP>"
-    traffic = traffic_from_profiles(kname, n_px)
+    traffic_bytes = traffic_from_profiles(kname, n_px)
+    traffic = None if traffic_bytes is None else round(traffic_bytes / (ms * 1e-3) / 1e9, 1)
     out = {
         "metric": "Gpixel/s inv+det & %HBM roofline, adjugate vs Cholesky, 1 MI355X",
         "value": round(value, 3), "unit": "Gpixel/s", "n_gpus": 1, "steps": args.steps,
@@ -228,6 +229,7 @@ def main():
         "config": WORKLOAD,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "traffic_bytes_per_launch": traffic_bytes,
                      "kernel": kname, "algorithmic_bytes_per_px": BYTES_PER_PX["f32"],
                      "launch": ops.get_launch(0, torch.float32, "adjugate", "compensated")},
     }
