@@ -179,7 +179,8 @@ size_t polsar_wishart_workspace_bytes(int dtype, int64_t n);
  * (grad) of S against Z (ops & POLSAR_OP_WISHART_FWD / _BWD).  Host array
  * `imgs`; the pointers inside are device pointers with the meaning above,
  * `loss` one device double per image.  grad_loss (device double, nullable =
- * 1.0) scales every gradient. */
+ * 1.0) scales every gradient.  Each image's outputs must not overlap its
+ * inputs or each other (POLSAR_E_ALIAS); in-place is not offered here. */
 enum { POLSAR_OP_INV_DET = 1, POLSAR_OP_WISHART_FWD = 2, POLSAR_OP_WISHART_BWD = 4 };
 typedef struct {
   int64_t n;

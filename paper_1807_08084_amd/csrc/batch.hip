@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 #include <vector>
 
 #include "../../include/polsar.h"
@@ -314,6 +315,30 @@ int polsar_batch_create(const polsar_image* imgs, int count, int dtype, int meth
     if (ops & POLSAR_OP_WISHART_BWD) {
       if (!planes_ok(m.grad, m.g_pitch)) return POLSAR_E_ARG;
       vec = vec && aligned(m.grad, 16) && (m.g_pitch * (int64_t)es) % 16 == 0;
+    }
+    {  // this image's outputs must not overlap its inputs or each other
+      auto rng = [&](const void* p, int planes, int64_t pitch, size_t e) {
+        const uintptr_t lo = (uintptr_t)p;
+        return std::make_pair(lo, p ? lo + (uintptr_t)(((planes - 1) * pitch + m.n) * (int64_t)e) : lo);
+      };
+      const bool wish = ops & (POLSAR_OP_WISHART_FWD | POLSAR_OP_WISHART_BWD);
+      const bool inv_op = ops & POLSAR_OP_INV_DET;
+      const std::pair<uintptr_t, uintptr_t> in[2] = {rng(m.z, 9, m.z_pitch, es),
+                                                     rng(wish ? m.sigma : nullptr, 9, m.s_pitch, es)};
+      const std::pair<uintptr_t, uintptr_t> out[5] = {
+          rng(inv_op ? m.inv : nullptr, 9, m.inv_pitch, es), rng(inv_op ? m.det : nullptr, 1, m.n, es),
+          rng(inv_op ? (const void*)m.status : nullptr, 1, m.n, 1),
+          rng((ops & POLSAR_OP_WISHART_BWD) ? m.grad : nullptr, 9, m.g_pitch, es),
+          rng((ops & POLSAR_OP_WISHART_FWD) ? m.ell : nullptr, 1, m.n, es)};
+      auto ov = [](std::pair<uintptr_t, uintptr_t> x, std::pair<uintptr_t, uintptr_t> y) {
+        return x.second > x.first && y.second > y.first && x.first < y.second && y.first < x.second;
+      };
+      for (int p = 0; p < 5; ++p) {
+        for (int q = 0; q < 2; ++q)
+          if (ov(out[p], in[q])) return POLSAR_E_ALIAS;
+        for (int q = p + 1; q < 5; ++q)
+          if (ov(out[p], out[q])) return POLSAR_E_ALIAS;
+      }
     }
     ImgDesc& d = h[i];
     d.z = m.z;

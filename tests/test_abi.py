@@ -124,6 +124,12 @@ def test_batch_and_copy_argument_errors(lib):
     assert lib.polsar_batch_create(arr, 1, L.F32, L.ADJUGATE, L.COMPENSATED, 8, None, None, 0, ctypes.byref(h)) == L.E_ARG
     assert lib.polsar_batch_create(arr, 1, L.F64, L.ADJUGATE, L.WIDE, 1, None, None, 0, ctypes.byref(h)) == L.E_UNSUPPORTED
     assert lib.polsar_batch_create(arr, 1, L.F32, L.ADJUGATE, L.PLAIN, 2, None, None, 0, ctypes.byref(h)) == L.E_ARG  # no sigma
+    ok = (L.Image * 1)()
+    ok[0].n, ok[0].z, ok[0].z_pitch = 64, FAKE, 64
+    ok[0].inv, ok[0].inv_pitch, ok[0].det = FAKE + 256, 64, FAKE3   # inverse planes inside z's span
+    assert lib.polsar_batch_create(ok, 1, L.F32, L.ADJUGATE, L.COMPENSATED, 1, None, None, 0, ctypes.byref(h)) == L.E_ALIAS
+    ok[0].inv, ok[0].det = FAKE2, FAKE2 + 1024                        # det inside the inverse planes
+    assert lib.polsar_batch_create(ok, 1, L.F32, L.ADJUGATE, L.COMPENSATED, 1, None, None, 0, ctypes.byref(h)) == L.E_ALIAS
     assert lib.polsar_batch_run(None, None) == L.E_ARG
     assert lib.polsar_batch_tiles(None) == -1
     assert lib.polsar_stream_copy(L.F32, 100, FAKE, 100, 5, FAKE2, 100, 10, None) == L.E_UNSUPPORTED
