@@ -2,12 +2,14 @@
 // determinant (Alg. 2; Alg. 1 for comparison) and the Wishart term.
 //
 // Every op is bandwidth-bound streaming over structure-of-arrays planes:
-// one lane owns V consecutive pixels (V = 16 bytes / element size, so each
-// plane access is one 128-bit global load or store), U such vectors per tile
-// per lane, and a tile is block*U vectors.  A lane issues all of its 9*U
-// (or 18*U) loads before any arithmetic, then all of its stores.  Pixels are
-// independent; nothing is shared between lanes except the fixed-order
-// reductions of the Wishart sum and the status counters.
+// one lane owns V consecutive pixels (V = 16 or 8 bytes / element size, so
+// each plane access is one 128- or 64-bit global load or store), U such
+// vectors per tile per lane, and a tile is block*U vectors.  A lane issues
+// all of its 9*U (or 18*U) loads before any arithmetic, then all of its
+// stores.  Pixels are independent; lanes share only the fixed-order
+// reductions of the Wishart sum, the status counters, and the wave's LDS
+// queue of FP32 pixels recomputed in FP64.  This file also holds the fused
+// multilook, block-diagonal and out-of-core streaming entry points.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -806,9 +808,8 @@ hipError_t dispatch_wishart(const polsar_launch& c, bool vec, WishartArgs& a, hi
   return dispatch_wishart_v<T, VW>(c, a, s);
 }
 
-int64_t max_wishart_tiles(int dtype, int64_t n) {
+int64_t max_wishart_tiles(int64_t n) {
   // smallest tile: 64 lanes x 1 vector of one element
-  (void)dtype;
   return std::max<int64_t>(1, (n + 63) / 64);
 }
 
@@ -948,7 +949,8 @@ int polsar_blockdiag_inv_det(int dtype, int method, int precision, int64_t n, in
 
 size_t polsar_wishart_workspace_bytes(int dtype, int64_t n) {
   if (n < 0) return 0;
-  return (size_t)max_wishart_tiles(dtype, n) * sizeof(double);
+  (void)dtype;  // the partials are FP64 for either storage type
+  return (size_t)max_wishart_tiles(n) * sizeof(double);
 }
 
 int polsar_wishart_loglik(int dtype, int pass, int64_t n, const void* sigma, int64_t s_pitch, const void* z,
