@@ -248,12 +248,50 @@ PX_HD bool adjugate_comp_try(const float z[9], float x[9], float& det, float* bo
   return ok;
 }
 
-// adjugate_comp_reroute: the FP64 recompute of one pixel, rounded to FP32.
+// Cofactors of an FP32 matrix in FP64.  A product of two FP32 numbers has at
+// most 48 significant bits, so FP64 holds every cofactor product exactly
+// (the exponent range covers all finite FP32 products); each component is
+// then a sum of three exact terms, and two error-free additions leave it as
+// hi + lo with |hi + lo - exact| <= u(|e1 + e2|) <= 2u^2 sum|products|,
+// within the Dot2 bound of cofactors_comp at a third fewer operations.
+PX_HD DW<double> sum3_exact(double p1, double p2, double p3) {
+  double s, e1, e2;
+  two_sum(p1, p2, s, e1);
+  two_sum(s, p3, s, e2);
+  return DW<double>{s, e1 + e2};
+}
+
+PX_HD void cofactors_widened(const double z[9], DW<double> c[9]) {
+  const double a = z[0], d = z[1], f = z[2], br = z[3], bi = z[4], cr = z[5], ci = z[6], er = z[7], ei = z[8];
+  c[0] = sum3_exact(d * f, -(er * er), -(ei * ei));
+  c[1] = sum3_exact(a * f, -(cr * cr), -(ci * ci));
+  c[2] = sum3_exact(a * d, -(br * br), -(bi * bi));
+  c[3] = sum3_exact(cr * er, ci * ei, -(br * f));
+  c[4] = sum3_exact(ci * er, -(cr * ei), -(bi * f));
+  c[5] = sum3_exact(br * er, -(bi * ei), -(cr * d));
+  c[6] = sum3_exact(br * ei, bi * er, -(ci * d));
+  c[7] = sum3_exact(cr * br, ci * bi, -(a * er));
+  c[8] = sum3_exact(ci * br, -(cr * bi), -(a * ei));
+}
+
+// adjugate_comp_reroute: the FP64 recompute of one pixel, rounded to FP32:
+// exact-product cofactors as above, then the compensated determinant, the
+// one division and the scaling of the FP64 compensated form.
 PX_HD int adjugate_comp_reroute(const float z[9], float x[9], float& det) {
   double zd[9], xd[9], dd;
 #pragma unroll
   for (int k = 0; k < 9; ++k) zd[k] = (double)z[k];
-  int st = adjugate_comp(zd, xd, dd);
+  int st;
+  {
+    DW<double> c[9];
+    const double no_mag[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // the bound is not used here
+    double bound;
+    cofactors_widened(zd, c);
+    dd = det_comp(zd, c, no_mag, bound);
+    const double t = 1.0 / dd;
+    scale_comp(c, t, xd);
+    st = classify(dd, t, zd[0], c[2].hi + c[2].lo);
+  }
 #pragma unroll
   for (int k = 0; k < 9; ++k) x[k] = (float)xd[k];
   det = (float)dd;

@@ -39,118 +39,10 @@ struct InvDetArgs {
   int64_t tiles;  // ceil(nvec / (block * U)), at least 1
 };
 
-// Compensated FP32 for one lane's V pixels with the FP64 recomputes gathered
-// across the wave: every pixel first takes the FP32 step; the pixels it
-// rejects are queued in this wave's LDS region (their 9 inputs), the wave's
-// lanes take one queued pixel each through the FP64 step, and the results go
-// back through LDS to the owning lanes.  A wave with nothing rejected skips
-// the queue.  With a fraction p of pixels rejected the FP64 step runs
-// ceil(64 V p / 64) times per wave instead of up to V times.
-// Queue: 64*V entries of REQ_FLOATS floats (9 inputs, then 9 outputs + det),
-// then 64*V status bytes.
-constexpr int REQ_FLOATS = 10;
-
-template <int V>
-__device__ __forceinline__ void comp_f32_wave(const float (&in)[9][V], float (&out)[9][V], float (&dt)[V],
-                                              int (&st)[V], float* q, uint8_t* qs) {
-  bool need[V];
-#pragma unroll
-  for (int l = 0; l < V; ++l) {
-    float zz[9], xx[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) zz[k] = in[k][l];
-    need[l] = !px::adjugate_comp_try(zz, xx, dt[l]);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) out[k][l] = xx[k];
-    st[l] = px::ST_OK;
-  }
-  unsigned long long mask[V];
-  int total = 0;
-#pragma unroll
-  for (int l = 0; l < V; ++l) {
-    mask[l] = __ballot(need[l]);
-    total += __popcll(mask[l]);
-  }
-  if (total == 0) return;  // uniform across the active lanes
-  const int lane = threadIdx.x & 63;
-  const unsigned long long below = lane == 0 ? 0ull : ((1ull << lane) - 1ull);
-  // the active lanes share the queue: rank among them, stride = their count
-  const unsigned long long active = __ballot(1);
-  const int rank = __popcll(active & below), nact = __popcll(active);
-  int base = 0;
-#pragma unroll
-  for (int l = 0; l < V; ++l) {
-    if (need[l]) {
-      const int pos = base + __popcll(mask[l] & below);
-#pragma unroll
-      for (int k = 0; k < 9; ++k) q[pos * REQ_FLOATS + k] = in[k][l];
-    }
-    base += __popcll(mask[l]);
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (int e = rank; e < total; e += nact) {
-    float zz[9], xx[9], d;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) zz[k] = q[e * REQ_FLOATS + k];
-    const int sst = px::adjugate_comp_reroute(zz, xx, d);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) q[e * REQ_FLOATS + k] = xx[k];
-    q[e * REQ_FLOATS + 9] = d;
-    qs[e] = (uint8_t)sst;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  base = 0;
-#pragma unroll
-  for (int l = 0; l < V; ++l) {
-    if (need[l]) {
-      const int pos = base + __popcll(mask[l] & below);
-#pragma unroll
-      for (int k = 0; k < 9; ++k) out[k][l] = q[pos * REQ_FLOATS + k];
-      dt[l] = q[pos * REQ_FLOATS + 9];
-      st[l] = qs[pos];
-    }
-    base += __popcll(mask[l]);
-  }
-}
-
-// LDS bytes of the FP32 compensated queue for one block.
-inline size_t comp_queue_bytes(int block, int v) {
-  const size_t entries = (size_t)block * v;  // 64*V per wave, block/64 waves
-  return entries * (REQ_FLOATS * sizeof(float) + 1);
-}
-
-// One pixel-vector of the inverse/determinant: load done by the caller.
-// COMPACT: the FP32 compensated form with the wave-level FP64 queue (needs
-// the block's dynamic LDS); otherwise the per-pixel function inline.
-template <class T, int OP, int V, bool NT, bool COMPACT = false>
-__device__ __forceinline__ void inv_det_vec(const InvDetArgs& a, const T (&in)[9][V], int64_t v,
-                                            unsigned& c0, unsigned& c1, unsigned& c2) {
-  T out[9][V], dt[V];
-  int st[V];
-  if constexpr (COMPACT) {
-    extern __shared__ __align__(16) float polsar_dyn_lds[];
-    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    float* q = polsar_dyn_lds + (size_t)w * 64 * V * REQ_FLOATS;
-    uint8_t* qs = (uint8_t*)(polsar_dyn_lds + (size_t)nw * 64 * V * REQ_FLOATS) + w * 64 * V;
-    comp_f32_wave<V>(in, out, dt, st, q, qs);
-#pragma unroll
-    for (int l = 0; l < V; ++l) tally(st[l], c0, c1, c2);
-  } else {
-#pragma unroll
-    for (int l = 0; l < V; ++l) {
-      T zz[9], xx[9];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) zz[k] = in[k][l];
-      st[l] = run_pixel<T, OP>(zz, xx, dt[l]);
-#pragma unroll
-      for (int k = 0; k < 9; ++k) out[k][l] = xx[k];
-      tally(st[l], c0, c1, c2);
-    }
-  }
+// Stores of one pixel-vector's results.
+template <class T, int V, bool NT>
+__device__ __forceinline__ void store_vec(const InvDetArgs& a, const T (&out)[9][V], const T (&dt)[V],
+                                          const int (&st)[V], int64_t v) {
   const int64_t e = v * V;
   if (a.inv) {
     T* inv = (T*)a.inv;
@@ -161,6 +53,129 @@ __device__ __forceinline__ void inv_det_vec(const InvDetArgs& a, const T (&in)[9
   if (a.status) store_status<V>(a.status + e, st);
 }
 
+// Compensated FP32 for one lane's U*V pixels (U vectors of V) with the FP64
+// recomputes gathered across the wave: every pixel first takes the FP32
+// step, and a pixel the step rejects is queued in the wave's LDS region
+// (its 9 inputs) right after its step, so its inputs need not stay in
+// registers.  Then the wave's lanes take one queued pixel each through the
+// FP64 step, and the results go back through LDS to the owning lanes,
+// which store whole vectors.  A wave with nothing rejected skips the
+// queue.  With a fraction p of pixels rejected the FP64 step runs
+// ceil(U V p) times per wave instead of up to U V times; queueing all U
+// vectors of a tile together fills the last round better than queueing
+// each vector on its own.  (Letting the recomputing lanes store their
+// pixels directly would free the owners earlier, but those 4-byte stores
+// land in lines the owners' vector stores already wrote and cost more
+// HBM traffic than the LDS round trip.)
+// Queue: 64*U*V entries of QUEUE_WORDS floats (9 inputs, then 9 outputs +
+// det), then 64*U*V status bytes.  valid[u] is false for vectors past the
+// end of the image; those take no step and are not queued.
+constexpr int QUEUE_WORDS = 10;
+
+template <int U, int V, bool NT>
+__device__ __forceinline__ void comp_f32_wave(const float* __restrict__ z, int64_t zp, const int64_t (&vec)[U],
+                                              const bool (&valid)[U], float (&out)[U][9][V], float (&dt)[U][V],
+                                              int (&st)[U][V], float* q, uint8_t* qs) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = lane == 0 ? 0ull : ((1ull << lane) - 1ull);
+  unsigned long long mask[U][V];
+  int total = 0;  // the wave's queued pixels
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    // vector u is loaded here, after the steps of vector u-1, which keeps
+    // the registers of two vectors' inputs free while the first is worked on
+    float in[9][V];
+    if (valid[u]) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) load_v<float, V, NT>(z + k * zp + vec[u] * V, in[k]);
+    }
+#pragma unroll
+    for (int l = 0; l < V; ++l) {
+      bool need = false;
+      st[u][l] = px::ST_OK;
+      if (valid[u]) {
+        float zz[9], xx[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) zz[k] = in[k][l];
+        need = !px::adjugate_comp_try(zz, xx, dt[u][l]);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) out[u][k][l] = xx[k];
+      }
+      mask[u][l] = __ballot(need);
+      if (need) {
+        const int pos = total + __popcll(mask[u][l] & below);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) q[pos * QUEUE_WORDS + k] = in[k][l];
+      }
+      total += __popcll(mask[u][l]);
+    }
+  }
+  if (total == 0) return;  // uniform across the active lanes
+  // the active lanes share the queue: rank among them, stride = their count
+  const unsigned long long active = __ballot(1);
+  const int rank = __popcll(active & below), nact = __popcll(active);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int e = rank; e < total; e += nact) {
+    float zz[9], xx[9], d;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) zz[k] = q[e * QUEUE_WORDS + k];
+    const int sst = px::adjugate_comp_reroute(zz, xx, d);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) q[e * QUEUE_WORDS + k] = xx[k];
+    q[e * QUEUE_WORDS + 9] = d;
+    qs[e] = (uint8_t)sst;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  int base = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int l = 0; l < V; ++l) {
+      if ((mask[u][l] >> lane) & 1ull) {
+        const int pos = base + __popcll(mask[u][l] & below);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) out[u][k][l] = q[pos * QUEUE_WORDS + k];
+        dt[u][l] = q[pos * QUEUE_WORDS + 9];
+        st[u][l] = qs[pos];
+      }
+      base += __popcll(mask[u][l]);
+    }
+}
+
+// LDS bytes of the FP32 compensated queue for one block, `slots` pixels per lane.
+inline size_t comp_queue_bytes(int block, int slots) {
+  const size_t entries = (size_t)block * slots;  // 64*slots per wave, block/64 waves
+  return entries * (QUEUE_WORDS * sizeof(float) + 1);
+}
+
+// Largest dynamic LDS a launch asks for.
+constexpr size_t MAX_DYN_LDS = 64 << 10;
+
+// One pixel-vector of the inverse/determinant with the per-pixel function
+// inline (every form but the FP32 compensated one of k_inv_det); the load
+// is done by the caller.
+template <class T, int OP, int V, bool NT>
+__device__ __forceinline__ void inv_det_vec(const InvDetArgs& a, const T (&in)[9][V], int64_t v,
+                                            unsigned& c0, unsigned& c1, unsigned& c2) {
+  T out[9][V], dt[V];
+  int st[V];
+#pragma unroll
+  for (int l = 0; l < V; ++l) {
+    T zz[9], xx[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) zz[k] = in[k][l];
+    st[l] = run_pixel<T, OP>(zz, xx, dt[l]);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) out[k][l] = xx[k];
+    tally(st[l], c0, c1, c2);
+  }
+  store_vec<T, V, NT>(a, out, dt, st, v);
+}
+
 template <class T, int OP, int V, int U, bool NT>
 __global__ __launch_bounds__(256) void k_inv_det(InvDetArgs a) {
   const T* __restrict__ z = (const T*)a.z;
@@ -168,19 +183,44 @@ __global__ __launch_bounds__(256) void k_inv_det(InvDetArgs a) {
   unsigned c0 = 0, c1 = 0, c2 = 0;
   for (int64_t tile = blockIdx.x; tile < a.tiles; tile += gridDim.x) {
     const int64_t v0 = tile * (int64_t)(B * U) + threadIdx.x;
-    T in[U][9][V];
+    if constexpr (OP == ADJ_COMP && std::is_same<T, float>::value) {
+      // all U vectors through the FP32 step and one shared FP64 queue
+      extern __shared__ __align__(16) float polsar_dyn_lds[];
+      const int w = threadIdx.x >> 6, nw = B >> 6;
+      float* q = polsar_dyn_lds + (size_t)w * 64 * U * V * QUEUE_WORDS;
+      uint8_t* qs = (uint8_t*)(polsar_dyn_lds + (size_t)nw * 64 * U * V * QUEUE_WORDS) + w * 64 * U * V;
+      int64_t vec[U];
+      bool valid[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t v = v0 + (int64_t)u * B;
-      if (v < a.nvec) {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) load_v<T, V, NT>(z + k * a.zp + v * V, in[u][k]);
+      for (int u = 0; u < U; ++u) {
+        vec[u] = v0 + (int64_t)u * B;
+        valid[u] = vec[u] < a.nvec;
       }
-    }
+      float out[U][9][V], dt[U][V];
+      int st[U][V];
+      comp_f32_wave<U, V, NT>(z, a.zp, vec, valid, out, dt, st, q, qs);
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t v = v0 + (int64_t)u * B;
-      if (v < a.nvec) inv_det_vec<T, OP, V, NT, OP == ADJ_COMP && std::is_same<T, float>::value>(a, in[u], v, c0, c1, c2);
+      for (int u = 0; u < U; ++u) {
+        if (!valid[u]) continue;
+#pragma unroll
+        for (int l = 0; l < V; ++l) tally(st[u][l], c0, c1, c2);
+        store_vec<T, V, NT>(a, out[u], dt[u], st[u], v0 + (int64_t)u * B);
+      }
+    } else {
+      T in[U][9][V];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t v = v0 + (int64_t)u * B;
+        if (v < a.nvec) {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) load_v<T, V, NT>(z + k * a.zp + v * V, in[u][k]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t v = v0 + (int64_t)u * B;
+        if (v < a.nvec) inv_det_vec<T, OP, V, NT>(a, in[u], v, c0, c1, c2);
+      }
     }
     if (V > 1 && tile == a.tiles - 1) {
       // the n mod V pixels after the last full vector, one per lane
@@ -504,8 +544,11 @@ polsar_launch default_launch(int op, int dtype, int method, int prec) {
     default:
       break;
   }
-  // op 0: winners of the autotuner on a 4096x4096 image
-  if (!chol && prec == POLSAR_COMPENSATED) return f64 ? polsar_launch{256, 1, 0, 1, 8, 3} : polsar_launch{128, 1, 0, 1, 16, 4};
+  // op 0: winners of the autotuner on a 4096x4096 image.  For FP32
+  // compensated the 8-byte access with three waves per SIMD also keeps
+  // pixels recomputed in FP64 cheap (images with many of them run best with
+  // 16-byte access at the same occupancy, which streams the rest slower).
+  if (!chol && prec == POLSAR_COMPENSATED) return f64 ? polsar_launch{256, 1, 0, 1, 8, 3} : polsar_launch{128, 1, 0, 1, 8, 8};
   if (chol && prec == POLSAR_PLAIN) return f64 ? polsar_launch{64, 1, 0, 1, 16, 5} : polsar_launch{256, 1, 0, 1, 8, 3};
   if (!chol && prec == POLSAR_PLAIN) return f64 ? polsar_launch{128, 1, 0, 1, 8, 0} : polsar_launch{256, 1, 0, 1, 8, 0};
   if (chol && prec == POLSAR_WIDE) return polsar_launch{64, 2, 0, 1, 16, 0};
@@ -531,7 +574,7 @@ int lds_per_cu() {
 size_t launch_lds(const polsar_launch& c, size_t need) {
   if (c.blocks_per_cu <= 0) return need;
   size_t pad = (size_t)lds_per_cu() / (size_t)(c.blocks_per_cu + 1) + 1024;
-  pad = std::min<size_t>(pad, 64 << 10);
+  pad = std::min<size_t>(pad, MAX_DYN_LDS);
   return std::max(need, pad);
 }
 
@@ -596,7 +639,8 @@ int op_code(int method, int prec) {
 // Launch helpers: pick the template instance for (V, U, NT).
 template <class T, int OP, int V, int U>
 hipError_t go_inv_det(const polsar_launch& c, int64_t grid, InvDetArgs& a, hipStream_t s) {
-  const size_t lds = launch_lds(c, (OP == ADJ_COMP && std::is_same<T, float>::value) ? comp_queue_bytes(c.block, V) : 0);
+  const size_t lds =
+      launch_lds(c, (OP == ADJ_COMP && std::is_same<T, float>::value) ? comp_queue_bytes(c.block, U * V) : 0);
   if (c.nontemporal)
     hipLaunchKernelGGL((k_inv_det<T, OP, V, U, true>), dim3((unsigned)grid), dim3(c.block), lds, s, a);
   else
@@ -604,21 +648,32 @@ hipError_t go_inv_det(const polsar_launch& c, int64_t grid, InvDetArgs& a, hipSt
   return hipGetLastError();
 }
 
+// Vectors per lane per tile actually used: the compensated FP32 kernel
+// takes at most two (four run out of registers), and one where the block's
+// shared FP64 queue for two would pass MAX_DYN_LDS.
+template <class T, int OP, int V>
+int inv_det_unroll(const polsar_launch& c) {
+  if constexpr (OP == ADJ_COMP && std::is_same<T, float>::value) {
+    const int u = c.unroll > 2 ? 2 : c.unroll;
+    return (u == 2 && comp_queue_bytes(c.block, 2 * V) > MAX_DYN_LDS) ? 1 : u;
+  } else {
+    return c.unroll;
+  }
+}
+
 template <class T, int OP, int V>
 hipError_t dispatch_inv_det_v(const polsar_launch& c, InvDetArgs& a, hipStream_t s) {
   a.nvec = a.n / V;
-  const int unroll = (c.unroll == 4 && OP == ADJ_COMP && std::is_same<T, float>::value) ? 2 : c.unroll;
+  const int unroll = inv_det_unroll<T, OP, V>(c);
   const int64_t per_tile = (int64_t)c.block * unroll;
   a.tiles = std::max<int64_t>(1, (a.nvec + per_tile - 1) / per_tile);
   int64_t grid = a.tiles;
   if (c.grid_per_cu > 0) grid = std::min<int64_t>(grid, (int64_t)c.grid_per_cu * device_cus());
-  if (c.unroll == 1) return go_inv_det<T, OP, V, 1>(c, grid, a, s);
-  // the compensated FP32 kernel with four vectors per lane runs out of
-  // registers; unroll 4 is taken as 2 there (the tile size follows)
+  if (unroll == 1) return go_inv_det<T, OP, V, 1>(c, grid, a, s);
   if constexpr (OP == ADJ_COMP && std::is_same<T, float>::value) {
     return go_inv_det<T, OP, V, 2>(c, grid, a, s);
   } else {
-    if (c.unroll == 2) return go_inv_det<T, OP, V, 2>(c, grid, a, s);
+    if (unroll == 2) return go_inv_det<T, OP, V, 2>(c, grid, a, s);
     return go_inv_det<T, OP, V, 4>(c, grid, a, s);
   }
 }

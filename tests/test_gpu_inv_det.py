@@ -203,3 +203,61 @@ def test_results_independent_of_launch(ops, small):
         ops.set_launch(0, torch.float32, "adjugate", "compensated", keep)
     for o in outs[1:]:
         assert all(torch.equal(a, b) for a, b in zip(outs[0], o))
+
+
+@pytest.fixture(scope="module")
+def rerouting():
+    """The precision recipe (N=3, per-pixel Sigma, lam in [1e-8, 1]) at 512x512:
+    about a third of the FP32 pixels are recomputed in FP64.  Reference: the
+    host build of the same per-pixel arithmetic."""
+    pixel = pytest.importorskip("host.pixel")
+    z = synth.workload_precision(seed=11, side=512).planes.reshape(9, -1).astype(np.float32)
+    inv, det, st, _ = pixel.adjugate_comp_f32(z)
+    assert 0.2 < np.mean(st == 1) < 0.5
+    return z, inv, det, st
+
+
+@pytest.mark.parametrize("cfg", [
+    {"block": 128, "unroll": 1, "grid_per_cu": 0, "nontemporal": 1, "vector_bytes": 16},
+    {"block": 64, "unroll": 1, "grid_per_cu": 1, "nontemporal": 0, "vector_bytes": 16},
+    {"block": 256, "unroll": 2, "grid_per_cu": 2, "nontemporal": 1, "vector_bytes": 16, "blocks_per_cu": 2},
+    {"block": 128, "unroll": 2, "grid_per_cu": 8, "nontemporal": 1, "vector_bytes": 8, "blocks_per_cu": 4},
+    {"block": 64, "unroll": 2, "grid_per_cu": 64, "nontemporal": 1, "vector_bytes": 16, "blocks_per_cu": 8},
+    {"block": 128, "unroll": 1, "grid_per_cu": 0, "nontemporal": 1, "vector_bytes": 8, "blocks_per_cu": 8},
+])
+@pytest.mark.parametrize("n_cut,offset", [(0, 0), (3, 0), (1, 1)])
+def test_reroute_queue_matches_host(ops, rerouting, cfg, n_cut, offset):
+    """FP32 compensated results, statuses and counters are bitwise those of
+    the host build for every launch shape: one tile per block and
+    persistent blocks, one vector per lane or two sharing one FP64 queue
+    (the 256-lane block with two falls back to one: its queue would not fit),
+    16- and 8-byte vectors, a ragged length, and planes off 16-byte
+    alignment (one pixel per lane)."""
+    z, inv_h, det_h, st_h = rerouting
+    n = z.shape[1] - n_cut - offset
+    sl = slice(offset, offset + n)
+    buf = torch.from_numpy(np.ascontiguousarray(z[:, :n + offset])).to("cuda")
+    zt = buf[:, offset:]
+    keep = ops.get_launch(0, torch.float32, "adjugate", "compensated")
+    try:
+        ops.set_launch(0, torch.float32, "adjugate", "compensated", cfg)
+        ctr = torch.zeros(3, dtype=torch.int64, device="cuda")
+        inv, det, st = ops.inv_det(zt, "adjugate", "compensated", status=True, counters=ctr)
+        torch.cuda.synchronize()
+    finally:
+        ops.set_launch(0, torch.float32, "adjugate", "compensated", keep)
+    s = st.cpu().numpy()
+    assert np.array_equal(s, st_h[sl])
+    assert np.array_equal(inv.cpu().numpy().view(np.uint32), inv_h[:, sl].view(np.uint32))
+    assert np.array_equal(det.cpu().numpy().view(np.uint32), det_h[sl].view(np.uint32))
+    c = ctr.cpu().numpy()
+    assert c[0] == np.sum(s == 2) and c[1] == np.sum(s == 1) and c[2] == np.sum(s == 3)
+
+
+def test_reroute_queue_in_place(ops, rerouting):
+    z, inv_h, det_h, _ = rerouting
+    zz = torch.from_numpy(z).to("cuda")
+    _, det, _ = ops.inv_det(zz, "adjugate", "compensated", inv=zz)
+    torch.cuda.synchronize()
+    assert np.array_equal(zz.cpu().numpy().view(np.uint32), inv_h.view(np.uint32))
+    assert np.array_equal(det.cpu().numpy().view(np.uint32), det_h.view(np.uint32))
