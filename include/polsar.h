@@ -231,7 +231,9 @@ void polsar_streamer_destroy(polsar_streamer* s);
  * 1 = wishart, 2 = multilook + inv_det, 3 = batch; ops 2 and 3 take unroll
  * 1, op 3 a persistent grid), dtype, method, precision.
  *   block        threads per block: 64, 128 or 256
- *   unroll       128-bit vectors per thread per tile: 1, 2 or 4
+ *   unroll       vectors per thread per tile: 1, 2 or 4 (the FP32
+ *                compensated inverse takes at most 2, sharing one FP64
+ *                queue; 1 where that queue would pass 64 KB of LDS)
  *   grid_per_cu  0 = one tile per block; k > 0 = persistent grid of k blocks
  *                per compute unit striding over tiles
  *   nontemporal  1 = streaming (non-temporal) loads and stores
@@ -246,8 +248,10 @@ int polsar_set_launch(int op, int dtype, int method, int precision, const polsar
 
 /* Times each candidate launch configuration of polsar_inv_det on the caller's
  * buffers (same arguments as polsar_inv_det; outputs are overwritten), `reps`
- * timed repetitions each after one warm-up, installs the fastest and returns
- * it with its mean time in milliseconds.  Synchronises `stream`. */
+ * timed repetitions each after one warm-up; the six fastest are timed again
+ * in three interleaved passes and ranked by their best pass.  Installs the
+ * winner and returns it with that mean time per call in milliseconds.
+ * Synchronises `stream`. */
 int polsar_autotune_inv_det(int dtype, int method, int precision, int64_t n,
                             const void* z, int64_t z_pitch, void* inv, int64_t inv_pitch,
                             void* det, int reps, polsar_launch* best, float* best_ms,

@@ -436,6 +436,88 @@ PX_HD Cx<T> herm(const T* v, int i, int j) {
   return i < j ? Cx<T>{v[k], v[k + 1]} : Cx<T>{v[k], -v[k + 1]};
 }
 
+// Products of entries of packed Hermitian matrices with the indices fixed at
+// compile time, so that the real diagonal entries cost real arithmetic only
+// (a product with a literal zero imaginary part would otherwise be kept:
+// IEEE arithmetic may not drop it).
+template <int I, int J, class T>
+PX_HD Cx<T> he(const T* v) {
+  if constexpr (I == J) {
+    return {v[I], T(0)};
+  } else {
+    constexpr int k = (I + J == 1) ? 3 : (I + J == 2) ? 5 : 7;
+    if constexpr (I < J) return {v[k], v[k + 1]};
+    else return {v[k], -v[k + 1]};
+  }
+}
+
+// acc (+)= A_IK B_KJ; FIRST: acc is set, not added to.
+template <int I, int K, int J, bool FIRST, class T>
+PX_HD void mac(Cx<T>& acc, const T* A, const T* B) {
+  const Cx<T> a = he<I, K>(A), b = he<K, J>(B);
+  if constexpr (I == K && K == J) {
+    acc.r = FIRST ? a.r * b.r : fma_(a.r, b.r, acc.r);
+    if (FIRST) acc.i = T(0);
+  } else if constexpr (I == K) {
+    acc.r = FIRST ? a.r * b.r : fma_(a.r, b.r, acc.r);
+    acc.i = FIRST ? a.r * b.i : fma_(a.r, b.i, acc.i);
+  } else if constexpr (K == J) {
+    acc.r = FIRST ? a.r * b.r : fma_(a.r, b.r, acc.r);
+    acc.i = FIRST ? a.i * b.r : fma_(a.i, b.r, acc.i);
+  } else {
+    acc.r = fma_(-a.i, b.i, FIRST ? a.r * b.r : fma_(a.r, b.r, acc.r));
+    acc.i = fma_(a.i, b.r, FIRST ? a.r * b.i : fma_(a.r, b.i, acc.i));
+  }
+}
+
+// Row I of the full product A B of packed Hermitian A, B.
+template <int I, class T>
+PX_HD void mat_row(const T* A, const T* B, Cx<T> (&row)[3]) {
+  mac<I, 0, 0, true>(row[0], A, B);
+  mac<I, 1, 0, false>(row[0], A, B);
+  mac<I, 2, 0, false>(row[0], A, B);
+  mac<I, 0, 1, true>(row[1], A, B);
+  mac<I, 1, 1, false>(row[1], A, B);
+  mac<I, 2, 1, false>(row[1], A, B);
+  mac<I, 0, 2, true>(row[2], A, B);
+  mac<I, 1, 2, false>(row[2], A, B);
+  mac<I, 2, 2, false>(row[2], A, B);
+}
+
+// acc (+)= P_IK W_KJ for packed Hermitian P and a full complex W.
+template <int I, int K, int J, bool FIRST, class T>
+PX_HD void pw(Cx<T>& acc, const T* P, const Cx<T> (&W)[3][3]) {
+  const Cx<T> a = he<I, K>(P), b = W[K][J];
+  if constexpr (I == K) {
+    acc.r = FIRST ? a.r * b.r : fma_(a.r, b.r, acc.r);
+    acc.i = FIRST ? a.r * b.i : fma_(a.r, b.i, acc.i);
+  } else {
+    acc.r = fma_(-a.i, b.i, FIRST ? a.r * b.r : fma_(a.r, b.r, acc.r));
+    acc.i = fma_(a.i, b.r, FIRST ? a.r * b.i : fma_(a.r, b.i, acc.i));
+  }
+}
+
+// Entry (I, J), I != J, of P W.
+template <int I, int J, class T>
+PX_HD Cx<T> herm_w(const T* P, const Cx<T> (&W)[3][3]) {
+  Cx<T> q;
+  pw<I, 0, J, true>(q, P, W);
+  pw<I, 1, J, false>(q, P, W);
+  pw<I, 2, J, false>(q, P, W);
+  return q;
+}
+
+// Real part of the diagonal entry (I, I) of P W (the entry of P Z P there is
+// real; its imaginary part is not formed).
+template <int I, class T>
+PX_HD T herm_w_diag(const T* P, const Cx<T> (&W)[3][3]) {
+  T q = P[I] * W[I][I].r;
+  if constexpr (I != 0) { const Cx<T> a = he<I, 0>(P); q = fma_(-a.i, W[0][I].i, fma_(a.r, W[0][I].r, q)); }
+  if constexpr (I != 1) { const Cx<T> a = he<I, 1>(P); q = fma_(-a.i, W[1][I].i, fma_(a.r, W[1][I].r, q)); }
+  if constexpr (I != 2) { const Cx<T> a = he<I, 2>(P); q = fma_(-a.i, W[2][I].i, fma_(a.r, W[2][I].r, q)); }
+  return q;
+}
+
 template <class T>
 PX_HD int wishart_pixel(const T s[9], const T z[9], T n_looks, bool want_ell, T& ell, bool want_grad, T grad[9],
                         T gscale) {
@@ -455,33 +537,21 @@ PX_HD int wishart_pixel(const T s[9], const T z[9], T n_looks, bool want_ell, T&
     for (int k = 0; k < 9; ++k) P[k] = t * c[k];
     // W = Z P, all nine entries
     Cx<T> W[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        Cx<T> acc = cmul(herm(z, i, 0), herm(P, 0, j));
-        acc = cadd(acc, cmul(herm(z, i, 1), herm(P, 1, j)));
-        acc = cadd(acc, cmul(herm(z, i, 2), herm(P, 2, j)));
-        W[i][j] = acc;
-      }
+    mat_row<0>(z, P, W[0]);
+    mat_row<1>(z, P, W[1]);
+    mat_row<2>(z, P, W[2]);
     // Q = P W on the upper triangle; grad = g N (P - Q), off-diagonals doubled
-    const T gs = gscale * n_looks;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = i; j < 3; ++j) {
-        Cx<T> q = cmul(herm(P, i, 0), W[0][j]);
-        q = cadd(q, cmul(herm(P, i, 1), W[1][j]));
-        q = cadd(q, cmul(herm(P, i, 2), W[2][j]));
-        const Cx<T> p = herm(P, i, j);
-        if (i == j) {
-          grad[i] = gs * (p.r - q.r);
-        } else {
-          const int k = (i + j == 1) ? 3 : (i + j == 2) ? 5 : 7;
-          grad[k] = T(2) * gs * (p.r - q.r);
-          grad[k + 1] = T(2) * gs * (p.i - q.i);
-        }
-      }
+    const T gs = gscale * n_looks, gs2 = T(2) * gs;
+    grad[0] = gs * (P[0] - herm_w_diag<0>(P, W));
+    grad[1] = gs * (P[1] - herm_w_diag<1>(P, W));
+    grad[2] = gs * (P[2] - herm_w_diag<2>(P, W));
+    const Cx<T> q01 = herm_w<0, 1>(P, W), q02 = herm_w<0, 2>(P, W), q12 = herm_w<1, 2>(P, W);
+    grad[3] = gs2 * (P[3] - q01.r);
+    grad[4] = gs2 * (P[4] - q01.i);
+    grad[5] = gs2 * (P[5] - q02.r);
+    grad[6] = gs2 * (P[6] - q02.i);
+    grad[7] = gs2 * (P[7] - q12.r);
+    grad[8] = gs2 * (P[8] - q12.i);
   }
   return st;
 }
