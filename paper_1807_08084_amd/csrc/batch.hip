@@ -3,13 +3,14 @@
 // The images' pixels are cut into tiles of `block` vectors (one vector per
 // lane, V pixels per vector on the 128-bit path), numbered consecutively
 // image after image.  One persistent grid (k blocks per compute unit)
-// strides over the global tile numbers; a block finds its image by binary
-// search over the images' first tiles.  Per tile it loads Z once and, as the
-// batch asks, writes the inverse/determinant of Z, and the Wishart term and
-// gradient of S against the same Z.  Wishart partial sums are kept per tile
-// and reduced per image in a fixed order by a second kernel, so the losses
-// do not depend on the grid.  Both launches are captured in one HIP graph at
-// creation; running the batch is one graph launch.
+// strides over the global tile numbers; a block finds the image of its first
+// tile by binary search over the images' first tiles and moves forward from
+// there.  Per tile it loads Z once and, as the batch asks, writes the
+// inverse/determinant of Z, and the Wishart term and gradient of S against
+// the same Z.  Wishart partial sums are kept per tile and reduced per
+// image in a fixed order by a second kernel, so the losses do not depend
+// on the grid.  Both launches are captured in one HIP graph at creation;
+// running the batch is one graph launch.
 //
 // The per-pixel functions are those of the per-call kernels, so every
 // per-pixel output is bitwise equal to a per-image call; the per-image loss
@@ -18,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -63,55 +65,88 @@ struct BatchArgs {
 template <class T, int OP, int V, bool NT>
 __device__ __forceinline__ double batch_tile(const BatchArgs& a, const ImgDesc& d, int64_t lt, T gscale,
                                              unsigned& c0, unsigned& c1, unsigned& c2) {
-  const T* __restrict__ Z = (const T*)d.z;
-  const T* __restrict__ S = (const T*)d.sigma;
+  // descriptor plane pointers, typed global (see gptr)
+  const gptr<const T> Z = to_global((const T*)d.z);
+  const gptr<const T> S = to_global((const T*)d.sigma);
+  const gptr<T> inv = to_global((T*)d.inv), det = to_global((T*)d.det);
+  const gptr<T> ell = to_global((T*)d.ell), grad = to_global((T*)d.grad);
+  const gptr<uint8_t> status = to_global(d.status);
   const int64_t v = lt * (int64_t)blockDim.x + threadIdx.x;
   const bool wish = a.do_fwd || a.do_bwd;
   double acc = 0.0;
   if (v < d.nvec) {
-    T z[9][V], s[9][V];
+    T z[9][V];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) load_v<T, V, NT>(Z + k * d.zp + v * V, z[k]);
-    if (wish)
-#pragma unroll
-      for (int k = 0; k < 9; ++k) load_v<T, V, NT>(S + k * d.sp + v * V, s[k]);
+    for (int k = 0; k < 9; ++k) gload_v<T, V, NT>(Z + k * d.zp + v * V, z[k]);
     const int64_t e = v * V;
     if (a.do_inv) {
       T out[9][V], dt[V];
       int st[V];
+      if constexpr (OP == ADJ_COMP && std::is_same<T, float>::value) {
+        // the FP32 step for the lane's V pixels, rejected pixels through the
+        // wave's shared FP64 queue (as in the per-call kernel)
+        extern __shared__ __align__(16) float polsar_dyn_lds[];
+        const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        float* q = polsar_dyn_lds + (size_t)w * 64 * V * QUEUE_WORDS;
+        uint8_t* qs = (uint8_t*)(polsar_dyn_lds + (size_t)nw * 64 * V * QUEUE_WORDS) + w * 64 * V;
+        const bool valid[1] = {true};
+        auto load = [&](int, float (&in)[9][V]) {
 #pragma unroll
-      for (int l = 0; l < V; ++l) {
-        T zz[9], xx[9];
+          for (int k = 0; k < 9; ++k)
 #pragma unroll
-        for (int k = 0; k < 9; ++k) zz[k] = z[k][l];
-        st[l] = run_pixel<T, OP>(zz, xx, dt[l]);
+            for (int l = 0; l < V; ++l) in[k][l] = z[k][l];
+        };
+        float o1[1][9][V], d1[1][V];
+        int s1[1][V];
+        comp_f32_wave<1, V>(load, valid, o1, d1, s1, q, qs);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) out[k][l] = xx[k];
-        tally(st[l], c0, c1, c2);
+        for (int l = 0; l < V; ++l) {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) out[k][l] = o1[0][k][l];
+          dt[l] = d1[0][l];
+          st[l] = s1[0][l];
+          tally(st[l], c0, c1, c2);
+        }
+      } else {
+#pragma unroll
+        for (int l = 0; l < V; ++l) {
+          T zz[9], xx[9];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) zz[k] = z[k][l];
+          st[l] = run_pixel<T, OP>(zz, xx, dt[l]);
+#pragma unroll
+          for (int k = 0; k < 9; ++k) out[k][l] = xx[k];
+          tally(st[l], c0, c1, c2);
+        }
       }
-      if (d.inv)
+      if (inv)
 #pragma unroll
-        for (int k = 0; k < 9; ++k) store_v<T, V, NT>((T*)d.inv + k * d.ip + e, out[k]);
-      if (d.det) store_v<T, V, NT>((T*)d.det + e, dt);
-      if (d.status) store_status<V>(d.status + e, st);
+        for (int k = 0; k < 9; ++k) gstore_v<T, V, NT>(inv + k * d.ip + e, out[k]);
+      if (det) gstore_v<T, V, NT>(det + e, dt);
+      if (status) gstore_status<V>(status + e, st);
     }
     if (wish) {
-      T ell[V], g[9][V];
+      // S is loaded after the inverse is stored, which keeps the registers
+      // of S free while the inverse is worked on
+      T s[9][V];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) gload_v<T, V, NT>(S + k * d.sp + v * V, s[k]);
+      T ellv[V], g[9][V];
 #pragma unroll
       for (int l = 0; l < V; ++l) {
         T ss[9], zz[9], gg[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) { ss[k] = s[k][l]; zz[k] = z[k][l]; }
-        px::wishart_pixel<T>(ss, zz, (T)d.n_looks, a.do_fwd, ell[l], a.do_bwd, gg, gscale);
-        if (a.do_fwd) acc += (double)ell[l];
+        px::wishart_pixel<T>(ss, zz, (T)d.n_looks, a.do_fwd, ellv[l], a.do_bwd, gg, gscale);
+        if (a.do_fwd) acc += (double)ellv[l];
         if (a.do_bwd)
 #pragma unroll
           for (int k = 0; k < 9; ++k) g[k][l] = gg[k];
       }
-      if (a.do_fwd && d.ell) store_v<T, V, NT>((T*)d.ell + e, ell);
+      if (a.do_fwd && ell) gstore_v<T, V, NT>(ell + e, ellv);
       if (a.do_bwd)
 #pragma unroll
-        for (int k = 0; k < 9; ++k) store_v<T, V, NT>((T*)d.grad + k * d.gp + e, g[k]);
+        for (int k = 0; k < 9; ++k) gstore_v<T, V, NT>(grad + k * d.gp + e, g[k]);
     }
   }
   if (V > 1 && lt == d.ntiles - 1) {
@@ -124,11 +159,11 @@ __device__ __forceinline__ double batch_tile(const BatchArgs& a, const ImgDesc& 
         T xx[9], dt;
         const int st = run_pixel<T, OP>(zz, xx, dt);
         tally(st, c0, c1, c2);
-        if (d.inv)
+        if (inv)
 #pragma unroll
-          for (int k = 0; k < 9; ++k) ((T*)d.inv)[k * d.ip + i] = xx[k];
-        if (d.det) ((T*)d.det)[i] = dt;
-        if (d.status) d.status[i] = (uint8_t)st;
+          for (int k = 0; k < 9; ++k) inv[k * d.ip + i] = xx[k];
+        if (det) det[i] = dt;
+        if (status) status[i] = (uint8_t)st;
       }
       if (wish) {
         T gg[9], el;
@@ -137,11 +172,11 @@ __device__ __forceinline__ double batch_tile(const BatchArgs& a, const ImgDesc& 
         px::wishart_pixel<T>(ss, zz, (T)d.n_looks, a.do_fwd, el, a.do_bwd, gg, gscale);
         if (a.do_fwd) {
           acc += (double)el;
-          if (d.ell) ((T*)d.ell)[i] = el;
+          if (ell) ell[i] = el;
         }
         if (a.do_bwd)
 #pragma unroll
-          for (int k = 0; k < 9; ++k) ((T*)d.grad)[k * d.gp + i] = gg[k];
+          for (int k = 0; k < 9; ++k) grad[k * d.gp + i] = gg[k];
       }
     }
   }
@@ -149,17 +184,24 @@ __device__ __forceinline__ double batch_tile(const BatchArgs& a, const ImgDesc& 
 }
 
 template <class T, int OP, bool NT, int VW>
-__global__ __launch_bounds__(256) void k_batch(BatchArgs a) {
+__global__ __launch_bounds__(256) void k_batch(BatchArgs a, const ImgDesc* __restrict__ img) {
   const T gscale = a.do_bwd ? (a.grad_loss ? (T)*a.grad_loss : T(1)) : T(1);
   unsigned c0 = 0, c1 = 0, c2 = 0;
-  for (int64_t t = blockIdx.x; t < a.total_tiles; t += gridDim.x) {
-    // image owning global tile t: last i with img[i].tile0 <= t
-    int lo = 0, hi = a.count - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (a.img[mid].tile0 <= t) lo = mid; else hi = mid - 1;
+  // image owning the block's first tile: last i with img[i].tile0 <= t, by
+  // binary search; later tiles only move forward, by a short linear scan
+  // (a dependent chain of descriptor loads per tile would stall the block)
+  int cur = 0;
+  {
+    const int64_t t = blockIdx.x;
+    int hi = a.count - 1;
+    while (cur < hi) {
+      const int mid = (cur + hi + 1) >> 1;
+      if (img[mid].tile0 <= t) cur = mid; else hi = mid - 1;
     }
-    const ImgDesc& d = a.img[lo];
+  }
+  for (int64_t t = blockIdx.x; t < a.total_tiles; t += gridDim.x) {
+    while (cur + 1 < a.count && img[cur + 1].tile0 <= t) ++cur;
+    const ImgDesc& d = img[cur];
     const int64_t lt = t - d.tile0;
     const double acc = d.vec ? batch_tile<T, OP, VW, NT>(a, d, lt, gscale, c0, c1, c2)
                              : batch_tile<T, OP, 1, NT>(a, d, lt, gscale, c0, c1, c2);
@@ -213,11 +255,11 @@ hipError_t enqueue(const polsar_batch* b, hipStream_t s) {
     const dim3 g(b->grid), t(b->block);                                                                        \
     const size_t lds = b->lds;                                                                                 \
     if (b->half) {                                                                                            \
-      if (b->nt) hipLaunchKernelGGL((k_batch<T, OPV, true, VW / 2>), g, t, lds, s, b->args);                  \
-      else hipLaunchKernelGGL((k_batch<T, OPV, false, VW / 2>), g, t, lds, s, b->args);                       \
+      if (b->nt) hipLaunchKernelGGL((k_batch<T, OPV, true, VW / 2>), g, t, lds, s, b->args, b->d_img);                  \
+      else hipLaunchKernelGGL((k_batch<T, OPV, false, VW / 2>), g, t, lds, s, b->args, b->d_img);                       \
     } else {                                                                                                  \
-      if (b->nt) hipLaunchKernelGGL((k_batch<T, OPV, true, VW>), g, t, lds, s, b->args);                      \
-      else hipLaunchKernelGGL((k_batch<T, OPV, false, VW>), g, t, lds, s, b->args);                           \
+      if (b->nt) hipLaunchKernelGGL((k_batch<T, OPV, true, VW>), g, t, lds, s, b->args, b->d_img);                      \
+      else hipLaunchKernelGGL((k_batch<T, OPV, false, VW>), g, t, lds, s, b->args, b->d_img);                           \
     }                                                                                                         \
   } while (0)
   if (b->dtype == POLSAR_F32) {
@@ -371,7 +413,10 @@ int polsar_batch_create(const polsar_image* imgs, int count, int dtype, int meth
   b->block = block;
   b->nt = use.nontemporal;
   b->half = half ? 1 : 0;
-  b->lds = polsar_launch_lds_bytes(use, 0);
+  // the FP32 compensated inverse queues rejected pixels in LDS: 64*VW
+  // entries per wave (the one-element path uses the front of that)
+  const bool queued = b->op == ADJ_COMP && dtype == POLSAR_F32 && (ops & POLSAR_OP_INV_DET);
+  b->lds = polsar_launch_lds_bytes(use, queued ? comp_queue_bytes(block, VW) : 0);
   b->total_tiles = tiles;
   const int gpc = grid_per_cu > 0 ? grid_per_cu : use.grid_per_cu;
   b->grid = (int)std::min<int64_t>(tiles, (int64_t)gpc * device_cus_b());

@@ -37,6 +37,50 @@ __device__ __forceinline__ void store_v(T* __restrict__ p, const T (&o)[V]) {
   }
 }
 
+// The same accesses through pointers typed in the global address space:
+// plane pointers read from a descriptor in memory carry no address space, so
+// the compiler would emit flat (generic) loads and stores for them; kernel
+// arguments are known to be global already.
+template <class T> using gptr = __attribute__((address_space(1))) T*;
+
+template <class T> __device__ __forceinline__ gptr<T> to_global(T* p) { return (gptr<T>)p; }
+
+template <class T, int V, bool NT>
+__device__ __forceinline__ void gload_v(gptr<const T> p, T (&o)[V]) {
+  if constexpr (V == 1) {
+    o[0] = NT ? __builtin_nontemporal_load(p) : *p;
+  } else {
+    typedef typename VecOf<T, V>::type VT;
+    const VT v = NT ? __builtin_nontemporal_load((gptr<const VT>)p) : *(gptr<const VT>)p;
+#pragma unroll
+    for (int l = 0; l < V; ++l) o[l] = v[l];
+  }
+}
+
+template <class T, int V, bool NT>
+__device__ __forceinline__ void gstore_v(gptr<T> p, const T (&o)[V]) {
+  if constexpr (V == 1) {
+    if (NT) __builtin_nontemporal_store(o[0], p); else *p = o[0];
+  } else {
+    typedef typename VecOf<T, V>::type VT;
+    VT v;
+#pragma unroll
+    for (int l = 0; l < V; ++l) v[l] = o[l];
+    if (NT) __builtin_nontemporal_store(v, (gptr<VT>)p); else *(gptr<VT>)p = v;
+  }
+}
+
+template <int V>
+__device__ __forceinline__ void gstore_status(gptr<uint8_t> p, const int (&st)[V]) {
+  if constexpr (V == 4) {
+    *(gptr<uint32_t>)p = (uint32_t)st[0] | ((uint32_t)st[1] << 8) | ((uint32_t)st[2] << 16) | ((uint32_t)st[3] << 24);
+  } else if constexpr (V == 2) {
+    *(gptr<uint16_t>)p = (uint16_t)(st[0] | (st[1] << 8));
+  } else {
+    *p = (uint8_t)st[0];
+  }
+}
+
 template <int V>
 __device__ __forceinline__ void store_status(uint8_t* p, const int (&st)[V]) {
   if constexpr (V == 4) {
@@ -81,6 +125,105 @@ __device__ __forceinline__ int run_pixel(const T (&z)[9], T (&x)[9], T& det) {
   else if constexpr (OP == CHOL_PLAIN) return px::cholesky_plain(z, x, det);
   else if constexpr (OP == CHOL_COMP) return px::cholesky_fallback(z, x, det);
   else return px::cholesky_wide(z, x, det);
+}
+
+// ------------------------------------------------------------------ FP32 compensated, shared FP64 queue
+// Compensated FP32 for one lane's U*V pixels (U vectors of V) with the FP64
+// recomputes gathered across the wave: every pixel first takes the FP32
+// step, and a pixel the step rejects is queued in the wave's LDS region
+// (its 9 inputs) right after its step, so its inputs need not stay in
+// registers.  Then the wave's lanes take one queued pixel each through the
+// FP64 step, and the results go back through LDS to the owning lanes,
+// which store whole vectors.  A wave with nothing rejected skips the
+// queue.  With a fraction p of pixels rejected the FP64 step runs
+// ceil(U V p) times per wave instead of up to U V times; queueing all U
+// vectors of a tile together fills the last round better than queueing
+// each vector on its own.  (Letting the recomputing lanes store their
+// pixels directly, over placeholders the owners' vector stores wrote,
+// would free the owners earlier; measured, those scattered 4-byte stores
+// made the kernel slower than the LDS round trip.)
+// Queue: 64*U*V entries of QUEUE_WORDS floats (9 inputs, then 9 outputs +
+// det), then 64*U*V status bytes.  valid[u] is false for vectors past the
+// end of the image; those take no step and are not queued.  load(u, in)
+// fills the 9 planes of vector u.  Every lane of the wave that is active at
+// the call takes part (ballots); inactive lanes neither queue nor drain.
+constexpr int QUEUE_WORDS = 10;
+
+template <int U, int V, class Load>
+__device__ __forceinline__ void comp_f32_wave(const Load& load, const bool (&valid)[U], float (&out)[U][9][V],
+                                              float (&dt)[U][V], int (&st)[U][V], float* q, uint8_t* qs) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = lane == 0 ? 0ull : ((1ull << lane) - 1ull);
+  unsigned long long mask[U][V];
+  int total = 0;  // the wave's queued pixels
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    // vector u is fetched here (load(u, in)), after the steps of vector
+    // u-1, which keeps the registers of two vectors' inputs free while the
+    // first is worked on
+    float in[9][V];
+    if (valid[u]) load(u, in);
+#pragma unroll
+    for (int l = 0; l < V; ++l) {
+      bool need = false;
+      st[u][l] = px::ST_OK;
+      if (valid[u]) {
+        float zz[9], xx[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) zz[k] = in[k][l];
+        need = !px::adjugate_comp_try(zz, xx, dt[u][l]);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) out[u][k][l] = xx[k];
+      }
+      mask[u][l] = __ballot(need);
+      if (need) {
+        const int pos = total + __popcll(mask[u][l] & below);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) q[pos * QUEUE_WORDS + k] = in[k][l];
+      }
+      total += __popcll(mask[u][l]);
+    }
+  }
+  if (total == 0) return;  // uniform across the active lanes
+  // the active lanes share the queue: rank among them, stride = their count
+  const unsigned long long active = __ballot(1);
+  const int rank = __popcll(active & below), nact = __popcll(active);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int e = rank; e < total; e += nact) {
+    float zz[9], xx[9], d;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) zz[k] = q[e * QUEUE_WORDS + k];
+    const int sst = px::adjugate_comp_reroute(zz, xx, d);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) q[e * QUEUE_WORDS + k] = xx[k];
+    q[e * QUEUE_WORDS + 9] = d;
+    qs[e] = (uint8_t)sst;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  int base = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int l = 0; l < V; ++l) {
+      if ((mask[u][l] >> lane) & 1ull) {
+        const int pos = base + __popcll(mask[u][l] & below);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) out[u][k][l] = q[pos * QUEUE_WORDS + k];
+        dt[u][l] = q[pos * QUEUE_WORDS + 9];
+        st[u][l] = qs[pos];
+      }
+      base += __popcll(mask[u][l]);
+    }
+}
+
+// LDS bytes of the FP32 compensated queue for one block, `slots` pixels per lane.
+inline size_t comp_queue_bytes(int block, int slots) {
+  const size_t entries = (size_t)block * slots;  // 64*slots per wave, block/64 waves
+  return entries * (QUEUE_WORDS * sizeof(float) + 1);
 }
 
 // Deterministic block sum of one double per lane; result valid in lane 0

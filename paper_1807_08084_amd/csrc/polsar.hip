@@ -53,105 +53,6 @@ __device__ __forceinline__ void store_vec(const InvDetArgs& a, const T (&out)[9]
   if (a.status) store_status<V>(a.status + e, st);
 }
 
-// Compensated FP32 for one lane's U*V pixels (U vectors of V) with the FP64
-// recomputes gathered across the wave: every pixel first takes the FP32
-// step, and a pixel the step rejects is queued in the wave's LDS region
-// (its 9 inputs) right after its step, so its inputs need not stay in
-// registers.  Then the wave's lanes take one queued pixel each through the
-// FP64 step, and the results go back through LDS to the owning lanes,
-// which store whole vectors.  A wave with nothing rejected skips the
-// queue.  With a fraction p of pixels rejected the FP64 step runs
-// ceil(U V p) times per wave instead of up to U V times; queueing all U
-// vectors of a tile together fills the last round better than queueing
-// each vector on its own.  (Letting the recomputing lanes store their
-// pixels directly would free the owners earlier, but those 4-byte stores
-// land in lines the owners' vector stores already wrote and cost more
-// HBM traffic than the LDS round trip.)
-// Queue: 64*U*V entries of QUEUE_WORDS floats (9 inputs, then 9 outputs +
-// det), then 64*U*V status bytes.  valid[u] is false for vectors past the
-// end of the image; those take no step and are not queued.
-constexpr int QUEUE_WORDS = 10;
-
-template <int U, int V, bool NT>
-__device__ __forceinline__ void comp_f32_wave(const float* __restrict__ z, int64_t zp, const int64_t (&vec)[U],
-                                              const bool (&valid)[U], float (&out)[U][9][V], float (&dt)[U][V],
-                                              int (&st)[U][V], float* q, uint8_t* qs) {
-  const int lane = threadIdx.x & 63;
-  const unsigned long long below = lane == 0 ? 0ull : ((1ull << lane) - 1ull);
-  unsigned long long mask[U][V];
-  int total = 0;  // the wave's queued pixels
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    // vector u is loaded here, after the steps of vector u-1, which keeps
-    // the registers of two vectors' inputs free while the first is worked on
-    float in[9][V];
-    if (valid[u]) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) load_v<float, V, NT>(z + k * zp + vec[u] * V, in[k]);
-    }
-#pragma unroll
-    for (int l = 0; l < V; ++l) {
-      bool need = false;
-      st[u][l] = px::ST_OK;
-      if (valid[u]) {
-        float zz[9], xx[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) zz[k] = in[k][l];
-        need = !px::adjugate_comp_try(zz, xx, dt[u][l]);
-#pragma unroll
-        for (int k = 0; k < 9; ++k) out[u][k][l] = xx[k];
-      }
-      mask[u][l] = __ballot(need);
-      if (need) {
-        const int pos = total + __popcll(mask[u][l] & below);
-#pragma unroll
-        for (int k = 0; k < 9; ++k) q[pos * QUEUE_WORDS + k] = in[k][l];
-      }
-      total += __popcll(mask[u][l]);
-    }
-  }
-  if (total == 0) return;  // uniform across the active lanes
-  // the active lanes share the queue: rank among them, stride = their count
-  const unsigned long long active = __ballot(1);
-  const int rank = __popcll(active & below), nact = __popcll(active);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (int e = rank; e < total; e += nact) {
-    float zz[9], xx[9], d;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) zz[k] = q[e * QUEUE_WORDS + k];
-    const int sst = px::adjugate_comp_reroute(zz, xx, d);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) q[e * QUEUE_WORDS + k] = xx[k];
-    q[e * QUEUE_WORDS + 9] = d;
-    qs[e] = (uint8_t)sst;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  int base = 0;
-#pragma unroll
-  for (int u = 0; u < U; ++u)
-#pragma unroll
-    for (int l = 0; l < V; ++l) {
-      if ((mask[u][l] >> lane) & 1ull) {
-        const int pos = base + __popcll(mask[u][l] & below);
-#pragma unroll
-        for (int k = 0; k < 9; ++k) out[u][k][l] = q[pos * QUEUE_WORDS + k];
-        dt[u][l] = q[pos * QUEUE_WORDS + 9];
-        st[u][l] = qs[pos];
-      }
-      base += __popcll(mask[u][l]);
-    }
-}
-
-// LDS bytes of the FP32 compensated queue for one block, `slots` pixels per lane.
-inline size_t comp_queue_bytes(int block, int slots) {
-  const size_t entries = (size_t)block * slots;  // 64*slots per wave, block/64 waves
-  return entries * (QUEUE_WORDS * sizeof(float) + 1);
-}
-
 // Largest dynamic LDS a launch asks for.
 constexpr size_t MAX_DYN_LDS = 64 << 10;
 
@@ -189,16 +90,16 @@ __global__ __launch_bounds__(256) void k_inv_det(InvDetArgs a) {
       const int w = threadIdx.x >> 6, nw = B >> 6;
       float* q = polsar_dyn_lds + (size_t)w * 64 * U * V * QUEUE_WORDS;
       uint8_t* qs = (uint8_t*)(polsar_dyn_lds + (size_t)nw * 64 * U * V * QUEUE_WORDS) + w * 64 * U * V;
-      int64_t vec[U];
       bool valid[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        vec[u] = v0 + (int64_t)u * B;
-        valid[u] = vec[u] < a.nvec;
-      }
+      for (int u = 0; u < U; ++u) valid[u] = v0 + (int64_t)u * B < a.nvec;
+      auto load = [&](int u, float (&in)[9][V]) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) load_v<float, V, NT>(z + k * a.zp + (v0 + (int64_t)u * B) * V, in[k]);
+      };
       float out[U][9][V], dt[U][V];
       int st[U][V];
-      comp_f32_wave<U, V, NT>(z, a.zp, vec, valid, out, dt, st, q, qs);
+      comp_f32_wave<U, V>(load, valid, out, dt, st, q, qs);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (!valid[u]) continue;
@@ -863,10 +764,9 @@ hipError_t dispatch_wishart(const polsar_launch& c, bool vec, WishartArgs& a, hi
   return dispatch_wishart_v<T, VW>(c, a, s);
 }
 
-int64_t max_wishart_tiles(int64_t n) {
-  // smallest tile: 64 lanes x 1 vector of one element
-  return std::max<int64_t>(1, (n + 63) / 64);
-}
+// Wishart partial sums (one per tile) of any launch shape: the smallest
+// tile is 64 lanes x 1 vector of one element.
+int64_t max_wishart_partials(int64_t n) { return std::max<int64_t>(1, (n + 63) / 64); }
 
 }  // namespace
 
@@ -1005,7 +905,7 @@ int polsar_blockdiag_inv_det(int dtype, int method, int precision, int64_t n, in
 size_t polsar_wishart_workspace_bytes(int dtype, int64_t n) {
   if (n < 0) return 0;
   (void)dtype;  // the partials are FP64 for either storage type
-  return (size_t)max_wishart_tiles(n) * sizeof(double);
+  return (size_t)max_wishart_partials(n) * sizeof(double);
 }
 
 int polsar_wishart_loglik(int dtype, int pass, int64_t n, const void* sigma, int64_t s_pitch, const void* z,

@@ -76,7 +76,7 @@ def tune_batch(items, method: str = "adjugate", precision: str = "compensated", 
     from .batch import BatchPlan
     dtype = items[0]["z"].dtype
     best, best_ms = None, float("inf")
-    for b, g, vb, bpc in itertools.product((64, 128, 256), (2, 4, 8, 16), (16, 8), (0, 2, 4, 6)):
+    for b, g, vb, bpc in itertools.product((64, 128, 256), (2, 4, 8, 16, 32, 64), (16, 8), (0, 2, 4, 6)):
         if bpc and g > bpc:
             continue  # a persistent grid larger than what can be resident
         cfg = dict(block=b, unroll=1, grid_per_cu=g, nontemporal=1, vector_bytes=vb, blocks_per_cu=bpc)

@@ -132,3 +132,36 @@ def test_empty_sum_is_zero(ops):
     S = torch.empty((9, 0), dtype=torch.float64, device="cuda")
     loss, _, _ = ops.wishart_loglik(S, S.clone(), N, forward=True)
     assert loss.item() == 0.0
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("n_cut", [0, 77])
+def test_every_launch_shape_with_minimal_workspace(ops, case, dtype, n_cut):
+    """The loss matches the oracle and the gradient is bitwise the same for
+    every launch shape, each run with a workspace of exactly the size the
+    library asks for (one partial per tile of the smallest shape)."""
+    r = case["f64" if dtype == torch.float64 else "f32"]
+    n = r["z"].shape[1] - n_cut
+    S = torch.from_numpy(np.ascontiguousarray(r["s"][:, :n])).to("cuda", dtype)
+    Z = torch.from_numpy(np.ascontiguousarray(r["z"][:, :n])).to("cuda", dtype)
+    nbytes = ops.workspace_bytes(dtype, n)
+    assert nbytes == max(1, (n + 63) // 64) * 8
+    ref = math.fsum(r["eh"][:n]) + math.fsum(r["el"][:n])
+    keep = ops.get_launch(1, dtype, "adjugate", "plain")
+    grads = []
+    try:
+        for block in (64, 128, 256):
+            for unroll in (1, 2):
+                for vb, gpc in ((16, 0), (8, 8)):
+                    ops.set_launch(1, dtype, "adjugate", "plain", dict(block=block, unroll=unroll, grid_per_cu=gpc,
+                                                                       nontemporal=1, vector_bytes=vb,
+                                                                       blocks_per_cu=0))
+                    ws = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+                    loss, g, _ = ops.wishart_loglik(S, Z, N, forward=True, backward=True, workspace=ws)
+                    torch.cuda.synchronize()
+                    tol = 1e-12 if dtype == torch.float64 else 1e-5
+                    assert abs(loss.item() - ref) <= tol * abs(ref), (block, unroll, vb, gpc)
+                    grads.append(g)
+    finally:
+        ops.set_launch(1, dtype, "adjugate", "plain", keep)
+    assert all(torch.equal(grads[0], g) for g in grads[1:])
