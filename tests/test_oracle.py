@@ -357,3 +357,46 @@ def test_nlm_oracle_closed_forms():
     P = img.reshape(9, 8, 6)
     y, x = 3, 2
     assert np.allclose(out.reshape(9, 8, 6)[:, y, x], P[:, y - 1:y + 2, x - 1:x + 2].mean(axis=(1, 2)), rtol=1e-9)
+
+
+def test_boxcar_oracle():
+    """Boxcar multilook: the __float128 gather through multilook128 and the
+    plain FP64 shifted-sum construction agree; window counts match brute
+    force; r = 0 is S S^H (rank one, det 0); a constant image gives v v^H at
+    every pixel; an impulse reaches exactly the pixels within Chebyshev
+    distance r, with v v^H / |W| there."""
+    from oracle import boxcar
+    rng = np.random.default_rng(41)
+    for H, W, r in ((7, 9, 1), (5, 13, 2), (11, 6, 3), (3, 4, 3), (1, 17, 2)):
+        s = rng.standard_normal((6, H * W))
+        (zh, zl), mag = boxcar.boxcar128(s, H, W, r)
+        z64 = boxcar.boxcar64(s, H, W, r)
+        assert np.all(np.abs(z64 - zh - zl) <= 64 * 2.0 ** -53 * mag)
+        cnt = np.array([sum(1 for yy in range(H) for xx in range(W) if abs(yy - y) <= r and abs(xx - x) <= r)
+                        for y in range(H) for x in range(W)])
+        assert np.array_equal(boxcar.window_counts(H, W, r), cnt)
+        sub = rng.choice(H * W, size=min(H * W, 9), replace=False)
+        (sh, sl), _ = boxcar.boxcar128(s, H, W, r, pixels=sub)
+        assert np.array_equal(sh, zh[:, sub]) and np.array_equal(sl, zl[:, sub])
+    # r = 0: one look, Z = S S^H exactly, singular
+    s = rng.integers(-4, 5, size=(6, 12)).astype(np.float64)
+    (zh, zl), _ = boxcar.boxcar128(s, 3, 4, 0)
+    assert np.array_equal(zh, boxcar.outer_planes(s)) and np.all(zl == 0)
+    dets = np.linalg.det(oracle.full_from_planes(zh)).real
+    assert np.all(np.abs(dets) <= 1e-12 * (1 + np.abs(zh).max() ** 3))
+    # constant image
+    v = np.array([1.0, -2.0, 0.5, 3.0, -1.5, 0.25])
+    s = np.repeat(v[:, None], 8 * 5, axis=1)
+    (zh, zl), _ = boxcar.boxcar128(s, 8, 5, 2)
+    assert np.array_equal(zh, np.repeat(boxcar.outer_planes(v[:, None]), 40, axis=1)) and np.all(zl == 0)
+    # impulse at (3, 4) in a 9 x 10 image, r = 2
+    H, W, r, y0, x0 = 9, 10, 2, 3, 4
+    s = np.zeros((6, H * W))
+    s[:, y0 * W + x0] = v
+    z = boxcar.boxcar64(s, H, W, r)
+    counts = boxcar.window_counts(H, W, r)
+    ov = boxcar.outer_planes(v[:, None])[:, 0]
+    for p in range(H * W):
+        y, x = divmod(p, W)
+        want = ov / counts[p] if (abs(y - y0) <= r and abs(x - x0) <= r) else np.zeros(9)
+        assert np.array_equal(z[:, p], want)
