@@ -288,6 +288,18 @@ def main():
                          "frac_hbm": round(mb / (m_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                          "bytes_per_px": mb // n_px}
         del lk
+        # spatial (boxcar) multilook of a single-look image, 3x3 and 7x7 windows
+        # (LDS-staged tile + halo), inverse + det out; 24 B in + 40 B out per px
+        sl = ops.upload_planes(synth.workload_boxcar().astype(np.float32).reshape(6, 4096, 4096), torch.float32,
+                               dev)
+        for r in (1, 3):
+            b_ms = time_calls(lambda: ops.boxcar_inv_det(sl, r, "adjugate", "compensated"), ksteps, 3, torch)
+            bb = 64 * n_px
+            rows[f"boxcar_r{r}_f32"] = {"gpx_s": round(n_px / b_ms / 1e6, 3), "ms": round(b_ms, 4),
+                                        "GB_s": round(bb / (b_ms * 1e-3) / 1e9, 1),
+                                        "frac_hbm": round(bb / (b_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                                        "bytes_per_px": 64, "window": f"{2 * r + 1}x{2 * r + 1}"}
+        del sl
         # nonlocal-means filter, 23x23 window, on the inverse / det just computed
         zimg = z32.view(9, 4096, 4096)
         inv_img, det_img = inv.view(9, 4096, 4096), det.view(4096, 4096).contiguous()

@@ -109,6 +109,29 @@ int polsar_multilook_inv_det(int dtype, int method, int precision, int64_t n, in
                              void* inv, int64_t inv_pitch, void* det, uint8_t* status,
                              unsigned long long* counters, void* stream);
 
+/* Spatial (boxcar) multilook fused with the inverse and determinant: Eq. ZN
+ * with the looks of pixel (y, x) taken from its (2r+1) x (2r+1)
+ * neighbourhood in a single-look image of height x width pixels (row-major),
+ * the window clipped at the image border:
+ *   Z(y, x) = (1/|W|) sum_{(y', x') in W(y, x)} S(y', x') S(y', x')^H,
+ *   W(y, x) = [max(0, y-r), min(H-1, y+r)] x [max(0, x-r), min(W-1, x+r)],
+ * summed in FP64 (exact products for F32 input), rounded to the storage type,
+ * optionally stored, and inverted exactly as polsar_inv_det inverts that
+ * stored Z (same per-pixel function, same bits).
+ *   s       in: 6 planes (pitch s_pitch), Re/Im of S_HH, S_HV, S_VV
+ *   radius  r, 0..3 (windows 1x1 to 7x7)
+ *   z       out (nullable): the 9 packed planes of Z (pitch z_pitch)
+ *   inv, det, status, counters as for polsar_inv_det (at least one given).
+ * Errors: POLSAR_E_ARG for a bad mode, negative or over-large sizes
+ * (height, width <= 2^24, height*width <= 2^32) or radius; the plane checks,
+ * alignment and POLSAR_E_ALIAS (any two of s, z, inv, det, status
+ * overlapping) as for polsar_multilook_inv_det.  A block stages its tile and
+ * halo of S in LDS; the launch shape is fixed. */
+int polsar_boxcar_inv_det(int dtype, int method, int precision, int64_t height, int64_t width, int radius,
+                          const void* s, int64_t s_pitch, void* z, int64_t z_pitch,
+                          void* inv, int64_t inv_pitch, void* det, uint8_t* status,
+                          unsigned long long* counters, void* stream);
+
 /* Block-diagonal pixels (closing section: multifrequency data, whose matrix
  * is block diagonal with one Hermitian 3x3 block per band, each block
  * inverted by the proposed method): n_blocks blocks per pixel.

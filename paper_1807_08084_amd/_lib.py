@@ -59,6 +59,7 @@ def lib():
         i, i64, vp, d, sz = ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_double, ctypes.c_size_t
         L.polsar_inv_det.argtypes = [i, i, i, i64, vp, i64, vp, i64, vp, vp, vp, vp]
         L.polsar_multilook_inv_det.argtypes = [i, i, i, i64, i, vp, i64, vp, i64, vp, i64, vp, vp, vp, vp]
+        L.polsar_boxcar_inv_det.argtypes = [i, i, i, i64, i64, i, vp, i64, vp, i64, vp, i64, vp, vp, vp, vp]
         L.polsar_blockdiag_inv_det.argtypes = [i, i, i, i64, i, vp, i64, vp, i64, vp, vp, i64, vp, vp, vp]
         L.polsar_streamer_create.argtypes = [i, i, i, i64, ctypes.POINTER(vp)]
         L.polsar_streamer_run.argtypes = [vp, i64, vp, i64, vp, i64, vp, vp, vp]

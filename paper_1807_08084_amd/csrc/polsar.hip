@@ -9,7 +9,8 @@
 // stores.  Pixels are independent; lanes share only the fixed-order
 // reductions of the Wishart sum, the status counters, and the wave's LDS
 // queue of FP32 pixels recomputed in FP64.  This file also holds the fused
-// multilook, block-diagonal and out-of-core streaming entry points.
+// multilook (per-pixel looks, and the spatial boxcar form), block-diagonal
+// and out-of-core streaming entry points.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -220,6 +221,130 @@ __global__ __launch_bounds__(256) void k_multilook(MultilookArgs a) {
     }
   }
   if (a.o.counters) flush_counters(a.o.counters, c0, c1, c2);
+}
+
+// ------------------------------------------------------------------ boxcar multilook
+// Spatial multilook fused with the inverse: Eq. (ZN) with the looks of pixel
+// (y, x) taken from its (2R+1) x (2R+1) neighbourhood in a single-look
+// image, clipped at the border,
+//   Z(y, x) = (1/|W|) sum_{(y', x') in W(y, x)} S(y', x') S(y', x')^H.
+// A block (one wave) owns BOX_TW output columns of a strip of BOX_STRIP
+// rows and walks down it one input row at a time: the row's single-look
+// pixels (with an R-pixel halo each side, zeros outside the image, which add
+// nothing) are staged in LDS, double-buffered, while the next row is being
+// loaded; each lane forms the sum of its 2R+1 horizontal neighbours' outer
+// products in FP64 (exact products for FP32 input) and keeps the last 2R+1
+// such row sums in registers, oldest first (shifted down one slot per row,
+// so every index is fixed at compile time and the loop body, with its
+// inverse, exists once).  Once a lane holds the rows of its output's window
+// it adds them in ascending row order, divides by the clipped window size,
+// rounds Z to the storage type (optionally stores it) and inverts it with
+// the per-pixel function of the per-call kernel.  Each row sum is formed
+// once per strip, so the work per output is (2R+1) outer products and 2R+1
+// additions of nine components, plus the halo rows of the strip.
+constexpr int BOX_TW = 64, BOX_STRIP = 32, BOX_MAX_R = 3;
+
+struct BoxArgs {
+  const void* s;
+  int64_t sp;
+  void* z;
+  int64_t zp;
+  void* inv;
+  int64_t ip;
+  void* det;
+  uint8_t* status;
+  unsigned long long* counters;
+  int64_t H, W;
+  int64_t nbx;  // blocks across the image
+};
+
+template <class T, int OP, int R>
+__global__ __launch_bounds__(BOX_TW) void k_boxcar(BoxArgs a) {
+  constexpr int K = 2 * R + 1, SW = BOX_TW + 2 * R;
+  constexpr int P = (SW + BOX_TW - 1) / BOX_TW;  // staged pixels per lane and row
+  __shared__ T row[2][6][SW];
+  const T* __restrict__ S = (const T*)a.s;
+  const int lane = threadIdx.x;
+  const int64_t bx = (int64_t)blockIdx.x % a.nbx, by = (int64_t)blockIdx.x / a.nbx;
+  const int64_t x0 = bx * BOX_TW, ys = by * BOX_STRIP;
+  const int64_t ye = ys + BOX_STRIP < a.H ? ys + BOX_STRIP : a.H;
+  const int64_t y_first = ys - R, y_last = ye - 1 + R;  // rows staged (outside the image: zeros)
+  const int64_t gx = x0 + lane;
+  const int64_t cols = (gx + R < a.W ? gx + R : a.W - 1) - (gx - R > 0 ? gx - R : 0) + 1;
+  auto load_row = [&](int64_t y, T (&v)[P][6]) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) v[p][k] = T(0);
+      const int col = lane + p * BOX_TW;
+      const int64_t x = x0 - R + col;
+      if (col < SW && y >= 0 && y < a.H && x >= 0 && x < a.W) {
+        const int64_t i = y * a.W + x;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) v[p][k] = S[k * a.sp + i];
+      }
+    }
+  };
+  double ring[K][9];  // row sums of rows y - 2R .. y, oldest first
+#pragma unroll
+  for (int m = 0; m < K; ++m)
+#pragma unroll
+    for (int c = 0; c < 9; ++c) ring[m][c] = 0.0;
+  T pre[P][6];
+  unsigned c0 = 0, c1 = 0, c2 = 0;
+  load_row(y_first, pre);
+#pragma unroll 1
+  for (int64_t y = y_first; y <= y_last; ++y) {  // the same for every lane of the block
+    const int b = (int)((y - y_first) & 1);
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int col = lane + p * BOX_TW;
+      if (col < SW)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) row[b][k][col] = pre[p][k];
+    }
+    __syncthreads();
+    if (y + 1 <= y_last) load_row(y + 1, pre);  // in flight while this row is summed
+#pragma unroll
+    for (int m = 0; m + 1 < K; ++m)
+#pragma unroll
+      for (int c = 0; c < 9; ++c) ring[m][c] = ring[m + 1][c];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) ring[K - 1][c] = 0.0;
+#pragma unroll
+    for (int dx = 0; dx < K; ++dx) {
+      T s6[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) s6[k] = row[b][k][lane + dx];
+      px::look_accumulate(s6, ring[K - 1]);
+    }
+    // output row y - R, whose window rows y - 2R .. y the ring now holds
+    const int64_t yo = y - R;
+    if (yo >= ys && gx < a.W) {
+      double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int m = 0; m < K; ++m)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) acc[c] += ring[m][c];
+      const int64_t rows = (yo + R < a.H ? yo + R : a.H - 1) - (yo - R > 0 ? yo - R : 0) + 1;
+      const double cnt = (double)(rows * cols);
+      T zz[9], xx[9], dt;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) zz[c] = (T)(acc[c] / cnt);
+      const int64_t i = yo * a.W + gx;
+      if (a.z)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) ((T*)a.z)[c * a.zp + i] = zz[c];
+      const int st_px = run_pixel<T, OP>(zz, xx, dt);
+      tally(st_px, c0, c1, c2);
+      if (a.inv)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) ((T*)a.inv)[c * a.ip + i] = xx[c];
+      if (a.det) ((T*)a.det)[i] = dt;
+      if (a.status) a.status[i] = (uint8_t)st_px;
+    }
+  }
+  if (a.counters) flush_counters(a.counters, c0, c1, c2);
 }
 
 // ------------------------------------------------------------------ block diagonal
@@ -696,6 +821,45 @@ hipError_t launch_multilook(int dtype, int op, const polsar_launch& c, bool vec,
   }
 }
 
+// ---- boxcar launch: one block (one wave) per BOX_TW columns x BOX_STRIP rows,
+// a 1-D grid; the radius is a template parameter (the ring of row sums is
+// indexed at compile time)
+template <class T, int OP, int R>
+hipError_t go_boxcar_r(BoxArgs& a, hipStream_t s) {
+  a.nbx = (a.W + BOX_TW - 1) / BOX_TW;
+  const int64_t nby = (a.H + BOX_STRIP - 1) / BOX_STRIP;
+  hipLaunchKernelGGL((k_boxcar<T, OP, R>), dim3((unsigned)(a.nbx * nby)), dim3(BOX_TW), 0, s, a);
+  return hipGetLastError();
+}
+
+template <class T, int OP>
+hipError_t go_boxcar(BoxArgs& a, int r, hipStream_t s) {
+  switch (r) {
+    case 0: return go_boxcar_r<T, OP, 0>(a, s);
+    case 1: return go_boxcar_r<T, OP, 1>(a, s);
+    case 2: return go_boxcar_r<T, OP, 2>(a, s);
+    default: return go_boxcar_r<T, OP, 3>(a, s);
+  }
+}
+
+hipError_t launch_boxcar(int dtype, int op, BoxArgs& a, int r, hipStream_t s) {
+  if (dtype == POLSAR_F32) {
+    switch (op) {
+      case ADJ_PLAIN: return go_boxcar<float, ADJ_PLAIN>(a, r, s);
+      case ADJ_COMP: return go_boxcar<float, ADJ_COMP>(a, r, s);
+      case ADJ_WIDE: return go_boxcar<float, ADJ_WIDE>(a, r, s);
+      case CHOL_PLAIN: return go_boxcar<float, CHOL_PLAIN>(a, r, s);
+      case CHOL_COMP: return go_boxcar<float, CHOL_COMP>(a, r, s);
+      default: return go_boxcar<float, CHOL_WIDE>(a, r, s);
+    }
+  }
+  switch (op) {
+    case ADJ_PLAIN: return go_boxcar<double, ADJ_PLAIN>(a, r, s);
+    case ADJ_COMP: return go_boxcar<double, ADJ_COMP>(a, r, s);
+    default: return go_boxcar<double, CHOL_PLAIN>(a, r, s);
+  }
+}
+
 // ---- block-diagonal launch
 template <class T, int OP, int V>
 hipError_t dispatch_block_v(const polsar_launch& c, BlockArgs& a, hipStream_t s) {
@@ -862,6 +1026,40 @@ int polsar_multilook_inv_det(int dtype, int method, int precision, int64_t n, in
         (status == nullptr || ((uintptr_t)status % (16 / es)) == 0);
   const polsar_launch c = get_cfg(2, dtype, method, precision);
   if (launch_multilook(dtype, op_code(method, precision), c, vec, a, (hipStream_t)stream) != hipSuccess)
+    return POLSAR_E_HIP;
+  return POLSAR_OK;
+}
+
+int polsar_boxcar_inv_det(int dtype, int method, int precision, int64_t height, int64_t width, int radius,
+                          const void* s, int64_t s_pitch, void* z, int64_t z_pitch, void* inv, int64_t inv_pitch,
+                          void* det, uint8_t* status, unsigned long long* counters, void* stream) {
+  int r = check_mode(dtype, method, precision);
+  if (r) return r;
+  if (height < 0 || width < 0 || radius < 0 || radius > BOX_MAX_R) return POLSAR_E_ARG;
+  if (height > ((int64_t)1 << 24) || width > ((int64_t)1 << 24)) return POLSAR_E_ARG;
+  const int64_t n = height * width;
+  if (n > ((int64_t)1 << 32)) return POLSAR_E_ARG;  // one block per 64 x 32 strip, 1-D grid
+  const size_t es = esize(dtype);
+  if ((r = check_planes(s, s_pitch, n, es))) return r;
+  if (z && (r = check_planes(z, z_pitch, n, es))) return r;
+  if (inv && (r = check_planes(inv, inv_pitch, n, es))) return r;
+  if (det && ((uintptr_t)det % es)) return POLSAR_E_ALIGN;
+  if (counters && ((uintptr_t)counters % 8)) return POLSAR_E_ALIGN;
+  if (!z && !inv && !det && !status && !counters) return POLSAR_E_ARG;
+  if (n > 0) {
+    const Range rl = span(s, 6, s_pitch, n, es);
+    const Range rz = z ? span(z, 9, z_pitch, n, es) : Range{0, 0};
+    const Range ri = inv ? span(inv, 9, inv_pitch, n, es) : Range{0, 0};
+    const Range rd = det ? span(det, 1, n, n, es) : Range{0, 0};
+    const Range rs = status ? span(status, 1, n, n, 1) : Range{0, 0};
+    const Range all[5] = {rl, rz, ri, rd, rs};
+    for (int p = 0; p < 5; ++p)
+      for (int q = p + 1; q < 5; ++q)
+        if (all[p].hi > all[p].lo && all[q].hi > all[q].lo && overlap(all[p], all[q])) return POLSAR_E_ALIAS;
+  }
+  if (n == 0) return POLSAR_OK;
+  BoxArgs a{s, s_pitch, z, z_pitch, inv, inv_pitch, det, status, counters, height, width, 0};
+  if (launch_boxcar(dtype, op_code(method, precision), a, radius, (hipStream_t)stream) != hipSuccess)
     return POLSAR_E_HIP;
   return POLSAR_OK;
 }

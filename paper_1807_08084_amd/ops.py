@@ -128,6 +128,28 @@ def multilook_inv_det(looks: torch.Tensor, n_looks: int, method: str = "adjugate
     return z, inv, det, st
 
 
+def boxcar_inv_det(s: torch.Tensor, radius: int, method: str = "adjugate", precision: str = "compensated", *,
+                   want_z: bool = False, status: bool = False, counters: torch.Tensor | None = None, stream=None):
+    """Spatial (boxcar) multilook of a single-look image s (6, H, W) over a
+    (2r+1)^2 window clipped at the border, fused with the inverse/determinant.
+
+    Returns (z or None, inv, det, status or None), shaped (9, H, W) / (H, W)."""
+    dt = _dtype_code(s)
+    if s.dim() != 3 or s.shape[0] != 6 or not s.is_cuda or not s[0].is_contiguous():
+        raise ValueError("s must be GPU planes of shape (6, H, W), each contiguous")
+    H, W = int(s.shape[1]), int(s.shape[2])
+    shape = (H, W)
+    out = empty_planes(10, shape, s.dtype, s.device)
+    inv, det = out[:9], out[9]
+    z = empty_planes(9, shape, s.dtype, s.device) if want_z else None
+    st = torch.empty(shape, dtype=torch.uint8, device=s.device) if status else None
+    rc = L.lib().polsar_boxcar_inv_det(dt, _METHODS[method], _PRECS[precision], H, W, int(radius), _ptr(s),
+                                       s.stride(0), _ptr(z), z.stride(0) if z is not None else 0, _ptr(inv),
+                                       inv.stride(0), _ptr(det), _ptr(st), _ptr(counters), _stream(stream))
+    L.check(rc, "polsar_boxcar_inv_det")
+    return z, inv, det, st
+
+
 def blockdiag_inv_det(z: torch.Tensor, n_blocks: int, method: str = "adjugate", precision: str = "compensated",
                       *, block_det: bool = False, status: bool = False, counters: torch.Tensor | None = None,
                       stream=None):

@@ -212,6 +212,12 @@ def workload_scale(seed=1, rows=None, with_looks=False):
     return make_image(4096, 4096, 4, (4, 4), (1e-3, 1.0), seed, rows=rows, with_looks=with_looks)
 
 
+def workload_boxcar(seed=4, side=4096):
+    """Single-look image for the boxcar multilook: side x side, 4x4 regions,
+    lam in [1e-3, 1]; returns the (6, side*side) FP64 planes of S."""
+    return make_image(side, side, 1, (4, 4), (1e-3, 1.0), seed, with_looks=True).looks.reshape(6, -1)
+
+
 def workload_precision(seed=2, side=8192, rows=None):
     """8192x8192, N=3, per-pixel Sigma with lam in [1e-8, 1]."""
     return make_image(side, side, 3, (1, 1), (1e-8, 1.0), seed, per_pixel=True, rows=rows)

@@ -153,3 +153,24 @@ def test_multilook_blockdiag_streamer_argument_errors(lib):
     assert lib.polsar_streamer_create(L.F32, L.ADJUGATE, L.COMPENSATED, 0, ctypes.byref(h)) == L.E_ARG
     assert lib.polsar_streamer_create(L.F64, L.ADJUGATE, L.WIDE, 1024, ctypes.byref(h)) == L.E_UNSUPPORTED
     assert lib.polsar_streamer_run(None, 10, FAKE, 10, FAKE2, 10, FAKE3, None, None) == L.E_ARG
+
+
+def test_boxcar_argument_errors(lib):
+    """Every rejection happens before any launch (fake pointers)."""
+    bx = lib.polsar_boxcar_inv_det
+    ok = (L.F32, L.ADJUGATE, L.COMPENSATED)
+    # 10 x 10 image: planes of 100
+    assert bx(*ok, 10, 10, 4, FAKE, 100, None, 0, FAKE2, 100, FAKE3, None, None, None) == L.E_ARG   # radius > 3
+    assert bx(*ok, 10, 10, -1, FAKE, 100, None, 0, FAKE2, 100, FAKE3, None, None, None) == L.E_ARG
+    assert bx(*ok, -1, 10, 1, FAKE, 100, None, 0, FAKE2, 100, FAKE3, None, None, None) == L.E_ARG
+    assert bx(*ok, 1 << 25, 1, 1, FAKE, 1 << 25, None, 0, FAKE2, 1 << 25, FAKE3, None, None, None) == L.E_ARG
+    assert bx(*ok, 1 << 17, 1 << 17, 1, FAKE, 1 << 34, None, 0, FAKE2, 1 << 34, FAKE3, None, None, None) == L.E_ARG
+    assert bx(*ok, 10, 10, 1, FAKE, 99, None, 0, FAKE2, 100, FAKE3, None, None, None) == L.E_ARG       # pitch < n
+    assert bx(*ok, 10, 10, 1, None, 100, None, 0, FAKE2, 100, FAKE3, None, None, None) == L.E_ARG      # null s
+    assert bx(L.F64, L.ADJUGATE, L.WIDE, 10, 10, 1, FAKE, 100, None, 0, FAKE2, 100, FAKE3, None, None,
+              None) == L.E_UNSUPPORTED
+    assert bx(*ok, 10, 10, 1, FAKE + 2, 100, None, 0, FAKE2, 100, FAKE3, None, None, None) == L.E_ALIGN
+    assert bx(*ok, 10, 10, 1, FAKE, 100, None, 0, FAKE + 800, 100, FAKE3, None, None, None) == L.E_ALIAS  # inv in s
+    assert bx(*ok, 10, 10, 1, FAKE, 100, FAKE2, 100, FAKE2 + 400, 100, FAKE3, None, None, None) == L.E_ALIAS
+    assert bx(*ok, 10, 10, 1, FAKE, 100, None, 0, None, 0, None, None, None, None) == L.E_ARG       # no output
+    assert bx(*ok, 0, 10, 1, FAKE, 100, None, 0, FAKE2, 100, FAKE3, None, None, None) == L.OK        # empty
