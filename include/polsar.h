@@ -159,7 +159,8 @@ int polsar_blockdiag_inv_det(int dtype, int method, int precision, int64_t n, in
  *         polsar_inv_det returns them)
  *   out   out: 9 planes of the filtered covariance (pitch out_pitch)
  *   wsum  out (nullable): sum of the weights per pixel
- * radius <= 16, n_looks > 0, h > 0.  Outputs must not overlap inputs. */
+ * radius <= 16, n_looks > 0, h > 0; width <= 2^20, height <= 262140, else
+ * POLSAR_E_ARG.  Outputs must not overlap inputs. */
 enum { POLSAR_DIST_KL = 0, POLSAR_DIST_BHATTACHARYYA = 1 };
 int polsar_nlm_wishart(int dtype, int distance, int64_t height, int64_t width, int radius,
                        double n_looks, double h, const void* z, int64_t z_pitch,

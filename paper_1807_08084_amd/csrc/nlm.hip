@@ -148,7 +148,8 @@ extern "C" int polsar_nlm_wishart(int dtype, int distance, int64_t height, int64
   if (distance != POLSAR_DIST_KL && distance != POLSAR_DIST_BHATTACHARYYA) return POLSAR_E_ARG;
   if (height < 0 || width < 0 || radius < 0 || radius > MAX_R || !(n_looks > 0.0) || !(h > 0.0))
     return POLSAR_E_ARG;
-  if (height > (1 << 20) || width > (1 << 20)) return POLSAR_E_ARG;
+  // one block row of the grid per TH output rows, at most 65535 of them
+  if (width > (1 << 20) || height > (int64_t)TH * 65535) return POLSAR_E_ARG;
   const int64_t n = height * width;
   const size_t es = dtype == POLSAR_F64 ? 8 : 4;
   const int aux_planes = distance == POLSAR_DIST_KL ? 9 : 1;

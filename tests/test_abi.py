@@ -174,3 +174,18 @@ def test_boxcar_argument_errors(lib):
     assert bx(*ok, 10, 10, 1, FAKE, 100, FAKE2, 100, FAKE2 + 400, 100, FAKE3, None, None, None) == L.E_ALIAS
     assert bx(*ok, 10, 10, 1, FAKE, 100, None, 0, None, 0, None, None, None, None) == L.E_ARG       # no output
     assert bx(*ok, 0, 10, 1, FAKE, 100, None, 0, FAKE2, 100, FAKE3, None, None, None) == L.OK        # empty
+
+
+def test_nlm_argument_errors(lib):
+    nl = lib.polsar_nlm_wishart
+    args = lambda dt, dist, H, W, r, N=4.0, h=16.0: nl(dt, dist, H, W, r, N, h, FAKE, H * W, FAKE2, H * W,  # noqa: E731
+                                                       FAKE3, H * W, None, None)
+    assert args(L.F32, 0, 10, 10, 17) == L.E_ARG                  # radius > 16
+    assert args(L.F32, 2, 10, 10, 3) == L.E_ARG                   # unknown distance
+    assert args(L.F32, 0, 10, 10, 3, N=0.0) == L.E_ARG
+    assert args(L.F32, 0, 10, 10, 3, h=0.0) == L.E_ARG
+    assert args(L.F32, 0, 4 * 65535 + 1, 1, 3) == L.E_ARG         # grid rows
+    assert args(L.F64, 0, 4 * 65535 + 1, 1, 3) == L.E_ARG
+    assert args(L.F32, 0, 10, (1 << 20) + 1, 3) == L.E_ARG
+    assert nl(L.F32, 0, 10, 10, 3, 4.0, 16.0, FAKE, 100, FAKE2, 100, FAKE + 400, 100, None, None) == L.E_ALIAS
+    assert args(L.F32, 0, 0, 10, 3) == L.OK                       # empty
