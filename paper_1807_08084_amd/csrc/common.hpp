@@ -1,6 +1,8 @@
 // Device helpers shared by the per-call kernels and the batched kernel:
-// 128-bit plane access, status bytes, counters, a fixed-order block sum and
-// the op table mapping (method, precision) to the per-pixel function.
+// 128/64-bit plane access (through generic or global-space pointers), status
+// bytes, counters, the op table mapping (method, precision) to the
+// per-pixel function, the wave-shared FP64 queue of the FP32 compensated
+// form, and a fixed-order block sum.
 #pragma once
 
 #include <hip/hip_runtime.h>
