@@ -6,8 +6,11 @@
 // strides over the global tile numbers; a block finds the image of its first
 // tile by binary search over the images' first tiles and moves forward from
 // there.  Per tile it loads Z once and, as the batch asks, writes the
-// inverse/determinant of Z, and the Wishart term and gradient of S against
-// the same Z.  Wishart partial sums are kept per tile and reduced per
+// inverse/determinant of Z (FP32 compensated: rejected pixels through the
+// wave's FP64 queue, as in the per-call kernel), then loads S and writes the
+// Wishart term and gradient of S against the same Z.  The descriptor table
+// is a restrict argument (scalar loads) and the plane pointers read from it
+// are typed global, so the accesses are global rather than flat ones.  Wishart partial sums are kept per tile and reduced per
 // image in a fixed order by a second kernel, so the losses do not depend
 // on the grid.  Both launches are captured in one HIP graph at creation;
 // running the batch is one graph launch.
