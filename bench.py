@@ -98,9 +98,29 @@ def cpu_baseline(z64: np.ndarray, n_px: int, min_seconds: float = 10.0):
         el = time.perf_counter() - t0
         if el >= min_seconds or passes >= 1000:
             break
+    # the same oracle on one core, over the first 2^20 pixels, for about 4 s
+    m = min(n_px, 1 << 20)
+    sub = np.ascontiguousarray(z64[:, :m])
+    t1 = time.perf_counter()
+    passes1 = 0
+    while True:
+        oracle.ge(sub, nthreads=1)
+        passes1 += 1
+        el1 = time.perf_counter() - t1
+        if el1 >= 4.0 or passes1 >= 1000:
+            break
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": passes * n_px / el / 1e9, "unit": "Gpixel/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 Gaussian-elimination oracle (OpenMP, {threads} threads) over the whole "
-                      f"{n_px}-pixel image, {passes} passes, {el:.1f} s"}
+                      f"{n_px}-pixel image, {passes} passes, {el:.1f} s",
+            "value_1core": passes1 * m / el1 / 1e9,
+            "sample_1core": f"same oracle, 1 thread, first {m} pixels, {passes1} passes, {el1:.1f} s",
+            "cpu_model": model}
 
 
 def other_workloads(torch, ops, dev, steps):
