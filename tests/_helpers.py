@@ -31,3 +31,20 @@ def to_np(t):
 
 def flat9(a):
     return np.asarray(a, dtype=np.float64).reshape(9, -1)
+
+
+W9 = np.array([1, 1, 1, 2, 2, 2, 2, 2, 2], dtype=np.float64)[:, None]  # Frobenius weights of the packing
+
+
+def oracle_z_storage(zh, zl, mag, n_terms, u):
+    """The oracle's multilook Z rounded to the storage type (unit roundoff u),
+    and delta bounding the relative Frobenius distance from it to any Z that
+    meets the fused kernels' Z check (u |Z| + (4 n + 4) u64 mag per
+    component).  A fused kernel inverts its own Z, so its inverse may differ
+    from the oracle's inverse of this Z by about kappa * delta on top of the
+    inversion tolerance; both are computed from oracle values only."""
+    z = zh + zl
+    zt = z.astype(np.float32).astype(np.float64) if u == U32 else z
+    comp = 2 * u * np.abs(zh) + (4 * n_terms + 4) * U64 * mag
+    delta = np.sqrt((W9 * comp * comp).sum(0)) / np.sqrt((W9 * zh * zh).sum(0))
+    return zt, delta
