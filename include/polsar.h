@@ -252,8 +252,10 @@ int polsar_streamer_run(polsar_streamer* s, int64_t n, const void* z, int64_t z_
 void polsar_streamer_destroy(polsar_streamer* s);
 
 /* Launch configuration of the kernels, keyed by op (0 = inv_det,
- * 1 = wishart, 2 = multilook + inv_det, 3 = batch; ops 2 and 3 take unroll
- * 1, op 3 a persistent grid), dtype, method, precision.
+ * 1 = wishart, 2 = multilook + inv_det, 3 = batch, 4 = the copy probe; ops
+ * 2, 3 and 4 take unroll 1, op 3 a persistent grid, op 4 one tile per
+ * block; ops 1 and 4 are keyed with method 0 and precision 0), dtype,
+ * method, precision.
  *   block        threads per block: 64, 128 or 256
  *   unroll       vectors per thread per tile: 1, 2 or 4 (the FP32
  *                compensated inverse takes at most 2, sharing one FP64
@@ -283,7 +285,9 @@ int polsar_autotune_inv_det(int dtype, int method, int precision, int64_t n,
 
 /* Bandwidth probe: copies n_in planes of n elements (pitch src_pitch) to
  * n_out planes (pitch dst_pitch; plane k of dst takes plane k mod n_in) with
- * the same access pattern as the inverse kernels, for a measured ceiling. */
+ * the same access pattern as the inverse kernels, for a measured ceiling.
+ * (n_in, n_out) is (9, 10), (18, 9) or (1, 1); planes 16-byte aligned.
+ * Launch shape: op 4 of polsar_get_launch. */
 int polsar_stream_copy(int dtype, int64_t n, const void* src, int64_t src_pitch, int n_in,
                        void* dst, int64_t dst_pitch, int n_out, void* stream);
 

@@ -528,16 +528,16 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ parti
 }
 
 // ------------------------------------------------------------------ copy probe
-template <class T, int V, int NI, int NO>
+template <class T, int V, int NI, int NO, bool NT>
 __global__ __launch_bounds__(256) void k_copy(const T* __restrict__ src, int64_t sp, T* __restrict__ dst,
                                               int64_t dp, int64_t nvec, int64_t n) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v < nvec) {
     T in[NI][V];
 #pragma unroll
-    for (int k = 0; k < NI; ++k) load_v<T, V, true>(src + k * sp + v * V, in[k]);
+    for (int k = 0; k < NI; ++k) load_v<T, V, NT>(src + k * sp + v * V, in[k]);
 #pragma unroll
-    for (int k = 0; k < NO; ++k) store_v<T, V, true>(dst + k * dp + v * V, in[k % NI]);
+    for (int k = 0; k < NO; ++k) store_v<T, V, NT>(dst + k * dp + v * V, in[k % NI]);
   }
   if (blockIdx.x == 0) {
     const int64_t i = nvec * V + threadIdx.x;
@@ -567,6 +567,8 @@ polsar_launch default_launch(int op, int dtype, int method, int prec) {
       return f64 ? polsar_launch{256, 1, 0, 1, 8, 4} : polsar_launch{128, 1, 0, 1, 16, 0};
     case 3:
       return f64 ? polsar_launch{256, 1, 2, 1, 16, 6} : polsar_launch{256, 1, 16, 1, 16, 0};
+    case 4:  // copy probe: few waves in flight stream best
+      return polsar_launch{64, 1, 0, 1, 16, 5};
     default:
       break;
   }
@@ -613,7 +615,8 @@ polsar_launch get_cfg(int op, int dtype, int method, int prec) {
 bool valid_launch(const polsar_launch& c, int op) {
   if (c.block != 64 && c.block != 128 && c.block != 256) return false;
   if (c.unroll != 1 && c.unroll != 2 && !(op == 0 && c.unroll == 4)) return false;
-  if ((op == 2 || op == 3) && c.unroll != 1) return false;
+  if ((op == 2 || op == 3 || op == 4) && c.unroll != 1) return false;
+  if (op == 4 && c.grid_per_cu != 0) return false;
   if (op == 3 && c.grid_per_cu == 0) return false;
   if (c.grid_per_cu < 0 || c.grid_per_cu > 64) return false;
   if (c.nontemporal != 0 && c.nontemporal != 1) return false;
@@ -971,13 +974,13 @@ int polsar_device_compute_units(int* cus) {
 }
 
 int polsar_get_launch(int op, int dtype, int method, int precision, polsar_launch* out) {
-  if (!out || op < 0 || op > 3) return POLSAR_E_ARG;
+  if (!out || op < 0 || op > 4) return POLSAR_E_ARG;
   *out = get_cfg(op, dtype, method, precision);
   return POLSAR_OK;
 }
 
 int polsar_set_launch(int op, int dtype, int method, int precision, const polsar_launch* cfg) {
-  if (!cfg || op < 0 || op > 3 || !valid_launch(*cfg, op)) return POLSAR_E_ARG;
+  if (!cfg || op < 0 || op > 4 || !valid_launch(*cfg, op)) return POLSAR_E_ARG;
   std::lock_guard<std::mutex> g(g_mu);
   g_cfg[std::make_tuple(op, dtype, method, precision)] = *cfg;
   return POLSAR_OK;
@@ -1251,21 +1254,36 @@ int polsar_stream_copy(int dtype, int64_t n, const void* src, int64_t src_pitch,
   if (n > 0 && overlap(span(src, n_in, src_pitch, n, es), span(dst, n_out, dst_pitch, n, es))) return POLSAR_E_ALIAS;
   if (n == 0) return POLSAR_OK;
   hipStream_t s = (hipStream_t)stream;
-  const int VW = (int)(16 / es);
+  // launch shape: op 4 of the table (block, access width, non-temporal,
+  // resident-block cap); one vector per lane, one tile per block
+  const polsar_launch c = get_cfg(4, dtype, 0, 0);
+  const int VW = (int)(c.vector_bytes / es);
   const int64_t nvec = n / VW;
-  const int64_t grid = std::max<int64_t>(1, (nvec + 255) / 256);
+  const int64_t grid = std::max<int64_t>(1, (nvec + c.block - 1) / c.block);
+  const size_t lds = launch_lds(c, 0);
 #define POLSAR_COPY(T, V, NI, NO)                                                                              \
-  hipLaunchKernelGGL((k_copy<T, V, NI, NO>), dim3((unsigned)grid), dim3(256), 0, s, (const T*)src, src_pitch, \
-                     (T*)dst, dst_pitch, nvec, n)
+  do {                                                                                                        \
+    if (c.nontemporal)                                                                                        \
+      hipLaunchKernelGGL((k_copy<T, V, NI, NO, true>), dim3((unsigned)grid), dim3(c.block), lds, s,           \
+                         (const T*)src, src_pitch, (T*)dst, dst_pitch, nvec, n);                              \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_copy<T, V, NI, NO, false>), dim3((unsigned)grid), dim3(c.block), lds, s,          \
+                         (const T*)src, src_pitch, (T*)dst, dst_pitch, nvec, n);                              \
+  } while (0)
+#define POLSAR_COPY_V(T, V)                                                                                    \
+  do {                                                                                                        \
+    if (n_in == 9) POLSAR_COPY(T, V, 9, 10);                                                                  \
+    else if (n_in == 18) POLSAR_COPY(T, V, 18, 9);                                                            \
+    else POLSAR_COPY(T, V, 1, 1);                                                                             \
+  } while (0)
   if (dtype == POLSAR_F32) {
-    if (n_in == 9) POLSAR_COPY(float, 4, 9, 10);
-    else if (n_in == 18) POLSAR_COPY(float, 4, 18, 9);
-    else POLSAR_COPY(float, 4, 1, 1);
+    if (VW == 4) POLSAR_COPY_V(float, 4);
+    else POLSAR_COPY_V(float, 2);
   } else {
-    if (n_in == 9) POLSAR_COPY(double, 2, 9, 10);
-    else if (n_in == 18) POLSAR_COPY(double, 2, 18, 9);
-    else POLSAR_COPY(double, 2, 1, 1);
+    if (VW == 2) POLSAR_COPY_V(double, 2);
+    else POLSAR_COPY_V(double, 1);
   }
+#undef POLSAR_COPY_V
 #undef POLSAR_COPY
   return hipGetLastError() == hipSuccess ? POLSAR_OK : POLSAR_E_HIP;
 }

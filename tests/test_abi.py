@@ -113,6 +113,11 @@ def test_launch_table(lib):
     got = L.Launch()
     lib.polsar_get_launch(0, L.F64, L.CHOLESKY, L.PLAIN, ctypes.byref(got))
     assert got.as_dict() == good.as_dict()
+    # op 4, the copy probe: one tile per block, unroll 1; op 5 does not exist
+    assert lib.polsar_get_launch(4, L.F32, 0, 0, ctypes.byref(got)) == L.OK
+    assert got.unroll == 1 and got.grid_per_cu == 0
+    assert lib.polsar_set_launch(4, L.F32, 0, 0, ctypes.byref(good)) == L.E_ARG
+    assert lib.polsar_get_launch(5, L.F32, 0, 0, ctypes.byref(got)) == L.E_ARG
 
 
 def test_batch_and_copy_argument_errors(lib):
