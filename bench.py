@@ -109,6 +109,20 @@ def cpu_baseline(z64: np.ndarray, n_px: int, min_seconds: float = 10.0):
         el1 = time.perf_counter() - t1
         if el1 >= 4.0 or passes1 >= 1000:
             break
+    # the other oracle forms beside it, about 2 s each: the FP64 Cholesky form
+    # over the whole image, the __float128 elimination on a 2^16-pixel sample
+    def rate(fn, px):
+        t, k = time.perf_counter(), 0
+        while True:
+            fn()
+            k += 1
+            e = time.perf_counter() - t
+            if e >= 2.0 or k >= 1000:
+                return k * px / e / 1e9, k, e
+    chol_rate, chol_k, chol_e = rate(lambda: oracle.chol(z64, nthreads=threads), n_px)
+    q = min(n_px, 1 << 16)
+    sub128 = np.ascontiguousarray(z64[:, :q])
+    q_rate, q_k, q_e = rate(lambda: oracle.ge128(sub128, nthreads=threads), q)
     model = "unknown"
     try:
         with open("/proc/cpuinfo") as fh:
@@ -120,6 +134,12 @@ def cpu_baseline(z64: np.ndarray, n_px: int, min_seconds: float = 10.0):
                       f"{n_px}-pixel image, {passes} passes, {el:.1f} s",
             "value_1core": passes1 * m / el1 / 1e9,
             "sample_1core": f"same oracle, 1 thread, first {m} pixels, {passes1} passes, {el1:.1f} s",
+            "value_cholesky_f64": chol_rate,
+            "sample_cholesky_f64": f"FP64 Cholesky oracle, {threads} threads, whole image, {chol_k} passes, "
+                                   f"{chol_e:.1f} s",
+            "value_ge_float128": q_rate,
+            "sample_ge_float128": f"__float128 Gaussian-elimination oracle, {threads} threads, first {q} "
+                                  f"pixels, {q_k} passes, {q_e:.1f} s",
             "cpu_model": model}
 
 
@@ -235,6 +255,20 @@ def main():
 
     warm_done = warm(step, args.warmup, torch, min_seconds=0.5)
     ms = time_calls(step, args.steps, 0, torch)
+    # the spread of single launches, each between its own pair of events
+    # (after the timed region; not part of the value)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for a, b in evs:
+        a.record()
+        step()
+        b.record()
+    torch.cuda.synchronize()
+    per = np.array([a.elapsed_time(b) for a, b in evs])
+    launch_stats = {"n": int(per.size), "min": round(float(per.min()), 4),
+                    "median": round(float(np.median(per)), 4), "mean": round(float(per.mean()), 4),
+                    "max": round(float(per.max()), 4), "std": round(float(per.std()), 4),
+                    "gpx_s_at_median": round(n_px / float(np.median(per)) / 1e6, 3)}
     if args.probe:
         src1 = z32[0:1]
         dst1 = ops.empty_planes(1, n_px, torch.float32, dev)
@@ -259,6 +293,7 @@ def main():
                      "traffic_bytes_per_launch": traffic_bytes,
                      "kernel": kname, "algorithmic_bytes_per_px": BYTES_PER_PX["f32"],
                      "launch": ops.get_launch(0, torch.float32, "adjugate", "compensated")},
+        "launch_ms": launch_stats,
     }
 
     if not args.no_rows:
