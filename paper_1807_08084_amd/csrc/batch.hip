@@ -219,9 +219,7 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs a, const ImgDesc* __res
 // One block per image: fixed-order sum of its tiles' partials into loss.
 __global__ __launch_bounds__(256) void k_batch_reduce(const ImgDesc* __restrict__ img, const double* __restrict__ partial) {
   const ImgDesc& d = img[blockIdx.x];
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < d.ntiles; i += blockDim.x) s += partial[d.tile0 + i];
-  s = block_sum(s);
+  const double s = strided_sum(partial + d.tile0, d.ntiles);
   if (threadIdx.x == 0 && d.loss) *d.loss = s;
 }
 

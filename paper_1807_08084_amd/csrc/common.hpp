@@ -246,4 +246,26 @@ __device__ __forceinline__ double block_sum(double v) {
   return s;
 }
 
+// Fixed-order sum of p[0 .. count) by one block: lane t adds p[t],
+// p[t + B], p[t + 2B], ... in ascending order (B = blockDim.x), then
+// block_sum.  Loads are issued D at a time, so a lane waits for memory
+// about count / (B D) times instead of count / B; the order of the
+// additions, hence the result, is the same as one load at a time.
+// Result valid in lane 0 of wave 0.
+__device__ __forceinline__ double strided_sum(const double* __restrict__ p, int64_t count) {
+  constexpr int D = 16;
+  const int64_t B = blockDim.x;
+  double s = 0.0;
+  int64_t i = threadIdx.x;
+  for (; i + (D - 1) * B < count; i += D * B) {
+    double v[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) v[j] = p[i + j * B];
+#pragma unroll
+    for (int j = 0; j < D; ++j) s += v[j];
+  }
+  for (; i < count; i += B) s += p[i];
+  return block_sum(s);
+}
+
 }  // namespace polsar_dev

@@ -521,9 +521,7 @@ __global__ __launch_bounds__(256) void k_wishart(WishartArgs a) {
 // Fixed-order sum of `count` partials into *out (one block of 256 lanes).
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partial, int64_t count,
                                                 double* __restrict__ out) {
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < count; i += blockDim.x) s += partial[i];
-  s = block_sum(s);
+  const double s = strided_sum(partial, count);
   if (threadIdx.x == 0) *out = s;
 }
 
@@ -555,14 +553,16 @@ std::map<std::tuple<int, int, int, int>, polsar_launch> g_cfg;
 // non-temporal (streaming) loads and stores.
 // The Wishart kernel in FP64 with 16-byte accesses needs all 256 VGPRs (one
 // wave per SIMD); with 8-byte accesses it runs at three waves per SIMD and
-// 20% faster.  The batch kernel (op 3) is a persistent grid.  blocks_per_cu
+// 20% faster.  On the 2048x2048 image the Wishart kernel gains 7% (FP32) and
+// 15% (FP64) from 8-byte accesses and, in FP64, a cap of 4 blocks per CU;
+// on the 4096x4096 image these shapes are within 2% of the best.  The batch kernel (op 3) is a persistent grid.  blocks_per_cu
 // caps the resident blocks: with 4-5 waves per CU the 19 concurrent plane
 // streams of a 3x3 inverse reach ~82% of HBM peak, with more they contend.
 polsar_launch default_launch(int op, int dtype, int method, int prec) {
   const bool f64 = dtype == POLSAR_F64, chol = method == POLSAR_CHOLESKY;
   switch (op) {
-    case 1:
-      return f64 ? polsar_launch{256, 1, 0, 1, 8, 0} : polsar_launch{256, 1, 0, 1, 16, 0};
+    case 1:  // chosen on 2048x2048 and 4096x4096 images together
+      return f64 ? polsar_launch{128, 1, 0, 1, 8, 4} : polsar_launch{256, 1, 0, 1, 8, 0};
     case 2:
       return f64 ? polsar_launch{256, 1, 0, 1, 8, 4} : polsar_launch{128, 1, 0, 1, 16, 0};
     case 3:
