@@ -553,16 +553,15 @@ std::map<std::tuple<int, int, int, int>, polsar_launch> g_cfg;
 // non-temporal (streaming) loads and stores.
 // The Wishart kernel in FP64 with 16-byte accesses needs all 256 VGPRs (one
 // wave per SIMD); with 8-byte accesses it runs at three waves per SIMD and
-// 20% faster.  On the 2048x2048 image the Wishart kernel gains 7% (FP32) and
-// 15% (FP64) from 8-byte accesses and, in FP64, a cap of 4 blocks per CU;
-// on the 4096x4096 image these shapes are within 2% of the best.  The batch kernel (op 3) is a persistent grid.  blocks_per_cu
+// 20% faster; capped at 4 blocks of 128 lanes per CU it gains another 6-15%
+// on the 2048x2048 image and stays within 2% of the best on 4096x4096.  The batch kernel (op 3) is a persistent grid.  blocks_per_cu
 // caps the resident blocks: with 4-5 waves per CU the 19 concurrent plane
 // streams of a 3x3 inverse reach ~82% of HBM peak, with more they contend.
 polsar_launch default_launch(int op, int dtype, int method, int prec) {
   const bool f64 = dtype == POLSAR_F64, chol = method == POLSAR_CHOLESKY;
   switch (op) {
-    case 1:  // chosen on 2048x2048 and 4096x4096 images together
-      return f64 ? polsar_launch{128, 1, 0, 1, 8, 4} : polsar_launch{256, 1, 0, 1, 8, 0};
+    case 1:
+      return f64 ? polsar_launch{128, 1, 0, 1, 8, 4} : polsar_launch{256, 1, 0, 1, 16, 0};
     case 2:
       return f64 ? polsar_launch{256, 1, 0, 1, 8, 4} : polsar_launch{128, 1, 0, 1, 16, 0};
     case 3:
