@@ -170,6 +170,7 @@ def other_workloads(torch, ops, dev, steps):
     res["precision_8192_rerouted_fraction"] = round(int(ctr[1].item()) / n, 4)
     print(f"# precision workload done", file=sys.stderr, flush=True)
     del z, o
+    torch.cuda.empty_cache()  # next workload's planes in fresh segments
     # Wishart: 2048^2, N=8; fused forward + backward
     img, sig = synth.workload_wishart()
     n = img.planes[0].size
@@ -182,6 +183,7 @@ def other_workloads(torch, ops, dev, steps):
         res[f"wishart_2048_fwd_bwd_{tn}"] = {"gpx_s": round(n / ms / 1e6, 3), "ms": round(ms, 4),
                                              "GB_s": round(bpp * n / ms / 1e6, 1)}
         del zt, st, ws
+        torch.cuda.empty_cache()
     print(f"# wishart workload done", file=sys.stderr, flush=True)
     # batch: 64 images, FP32 compensated inverse + Wishart fwd + bwd, one graph vs per-image loop
     imgs = synth.workload_batch()
@@ -344,6 +346,7 @@ def main():
             rows[f"wishart_fwd_bwd_{tname}"] = {"gpx_s": round(n_px / w_ms / 1e6, 3), "ms": round(w_ms, 4),
                                                "GB_s": round(wgbs, 1), "frac_hbm": round(wgbs / PEAK_HBM_GBS, 4)}
             del sig, ws
+            torch.cuda.empty_cache()
         # fused multilook front end (N=4 looks in, inverse + det out), FP32
         lk = ops.upload_planes(img.looks.reshape(24, -1).astype(np.float32), torch.float32, dev)
         del img
@@ -356,6 +359,7 @@ def main():
                          "frac_hbm": round(mb / (m_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                          "bytes_per_px": mb // n_px}
         del lk
+        torch.cuda.empty_cache()
         # spatial (boxcar) multilook of a single-look image, 3x3 and 7x7 windows
         # (LDS-staged tile + halo), inverse + det out; 24 B in + 40 B out per px
         sl = ops.upload_planes(synth.workload_boxcar().astype(np.float32).reshape(6, 4096, 4096), torch.float32,
@@ -368,6 +372,7 @@ def main():
                                         "frac_hbm": round(bb / (b_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                                         "bytes_per_px": 64, "window": f"{2 * r + 1}x{2 * r + 1}"}
         del sl
+        torch.cuda.empty_cache()
         # nonlocal-means filter, 23x23 window, on the inverse / det just computed
         zimg = z32.view(9, 4096, 4096)
         inv_img, det_img = inv.view(9, 4096, 4096), det.view(4096, 4096).contiguous()
@@ -394,6 +399,7 @@ def main():
                                      "GB_s_pcie": round(BYTES_PER_PX["f32"] * n_px / (s_ms * 1e-3) / 1e9, 1),
                                      "chunk_px": 1 << 21, "note": "host pinned in and out, wall clock"}
         del zh, ih, dh
+        torch.cuda.empty_cache()
         adj = rows["adjugate_compensated_f32"]["ms"]
         out["rows"] = rows
         out["copy_ceiling_frac"] = round(rows["copy_9to10_f32"]["ms"] / ms, 4)
