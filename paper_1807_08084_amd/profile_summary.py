@@ -57,7 +57,10 @@ def _counter(db: str, counter: str):
 def traffic(fetch_db: str, write_db: str, out: str, command: str, n_px: int = 4096 * 4096) -> None:
     f = _counter(fetch_db, "FETCH_SIZE")
     w = _counter(write_db, "WRITE_SIZE")
-    probe = next(k for k in f if k.startswith("k_copy<float, 4, 1, 1>"))
+    def one_plane_copy(k):  # k_copy<float, V, 1, 1[, NT]>
+        args = k[k.find("<") + 1:k.rfind(">")].split(", ")
+        return k.startswith("k_copy<float,") and args[2:4] == ["1", "1"]
+    probe = next(k for k in f if one_plane_copy(k))
     kern = next(k for k in f if k.startswith("k_inv_det<float, 1,"))
     probe_bytes = 4 * n_px
     f_scale = probe_bytes / (f[probe] * 1024)
