@@ -148,11 +148,26 @@ def other_workloads(torch, ops, dev, steps):
     from paper_1807_08084_amd import synth
     from paper_1807_08084_amd.batch import BatchPlan
     res = {}
+    # 8192^2 with the 4096^2 recipe (N=4, 4x4 regions, lam in [1e-3, 1]): both forms, FP32 and FP64
+    img = synth.workload_scale8192()
+    n = img.planes[0].size
+    for dt, tn in ((torch.float32, "f32"), (torch.float64, "f64")):
+        z = ops.upload_planes(img.planes.reshape(9, -1), dt, dev)
+        o = ops.empty_planes(10, n, dt, dev)
+        for method, prec in (("adjugate", "compensated"), ("cholesky", "plain")):
+            ms = time_calls(lambda: ops.inv_det(z, method, prec, inv=o[:9], det=o[9]), steps, 3, torch)
+            gbs = BYTES_PER_PX[tn] * n / (ms * 1e-3) / 1e9
+            res[f"scale_8192_{method}_{prec}_{tn}"] = {"gpx_s": round(n / ms / 1e6, 3), "ms": round(ms, 4),
+                                                       "GB_s": round(gbs, 1),
+                                                       "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)}
+        del z, o
+        torch.cuda.empty_cache()
+    del img
+    print(f"# 8192^2 scale workload done", file=sys.stderr, flush=True)
     # precision: 8192^2, N=3, per-pixel Sigma, lam in [1e-8, 1]; FP32 compensated with reroute
     img = synth.workload_precision()
     z = ops.upload_planes(img.planes.reshape(9, -1).astype(np.float32), torch.float32, dev)
     n = z.shape[1]
-    del img
     o = ops.empty_planes(10, n, torch.float32, dev)
     ctr = torch.zeros(3, dtype=torch.int64, device=dev)
     ops.inv_det(z, "adjugate", "compensated", inv=o[:9], det=o[9], counters=ctr)
@@ -168,9 +183,20 @@ def other_workloads(torch, ops, dev, steps):
         "gpx_s": round(n / ms / 1e6, 3), "ms": round(ms, 4), "GB_s": round(76 * n / ms / 1e6, 1), "launch": cfg}
     ops.set_launch(0, torch.float32, "adjugate", "compensated", keep)
     res["precision_8192_rerouted_fraction"] = round(int(ctr[1].item()) / n, 4)
-    print(f"# precision workload done", file=sys.stderr, flush=True)
     del z, o
     torch.cuda.empty_cache()  # next workload's planes in fresh segments
+    # the FP64 kernels on the same image in FP64
+    z = ops.upload_planes(img.planes.reshape(9, -1), torch.float64, dev)
+    del img
+    o = ops.empty_planes(10, n, torch.float64, dev)
+    for prec in ("compensated", "plain"):
+        ms = time_calls(lambda: ops.inv_det(z, "adjugate", prec, inv=o[:9], det=o[9]), steps, 3, torch)
+        gbs = BYTES_PER_PX["f64"] * n / (ms * 1e-3) / 1e9
+        res[f"precision_8192_adjugate_{prec}_f64"] = {"gpx_s": round(n / ms / 1e6, 3), "ms": round(ms, 4),
+                                                      "GB_s": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)}
+    del z, o
+    torch.cuda.empty_cache()
+    print(f"# precision workload done", file=sys.stderr, flush=True)
     # Wishart: 2048^2, N=8; fused forward + backward
     img, sig = synth.workload_wishart()
     n = img.planes[0].size

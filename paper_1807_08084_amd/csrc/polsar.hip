@@ -571,13 +571,16 @@ polsar_launch default_launch(int op, int dtype, int method, int prec) {
     default:
       break;
   }
-  // op 0: winners of the autotuner on a 4096x4096 image.  For FP32
-  // compensated the 8-byte access with three waves per SIMD also keeps
-  // pixels recomputed in FP64 cheap (images with many of them run best with
-  // 16-byte access at the same occupancy, which streams the rest slower).
-  if (!chol && prec == POLSAR_COMPENSATED) return f64 ? polsar_launch{256, 1, 0, 1, 8, 3} : polsar_launch{128, 1, 0, 1, 8, 8};
+  // op 0: winners of the autotuner on 4096x4096 and 8192x8192 images of the
+  // same recipe, taken together.  For FP32 compensated the 8-byte access
+  // with three waves per SIMD also keeps pixels recomputed in FP64 cheap
+  // (images with many of them run best with 16-byte access at the same
+  // occupancy, which streams the rest slower).  The FP64 adjugate runs 11%
+  // faster on 8192x8192 with 16-byte accesses and 6 single-wave blocks per
+  // CU than with 12 waves of 8-byte accesses (1% slower on 4096x4096).
+  if (!chol && prec == POLSAR_COMPENSATED) return f64 ? polsar_launch{64, 1, 0, 1, 16, 6} : polsar_launch{128, 1, 0, 1, 8, 8};
   if (chol && prec == POLSAR_PLAIN) return f64 ? polsar_launch{64, 1, 0, 1, 16, 5} : polsar_launch{256, 1, 0, 1, 8, 3};
-  if (!chol && prec == POLSAR_PLAIN) return f64 ? polsar_launch{128, 1, 0, 1, 8, 0} : polsar_launch{256, 1, 0, 1, 8, 0};
+  if (!chol && prec == POLSAR_PLAIN) return f64 ? polsar_launch{64, 1, 0, 1, 16, 6} : polsar_launch{64, 1, 0, 1, 16, 5};
   if (chol && prec == POLSAR_WIDE) return polsar_launch{64, 2, 0, 1, 16, 0};
   if (chol) return polsar_launch{64, 1, 0, 1, 16, 0};
   return polsar_launch{128, 1, 0, 1, 8, 0};  // adjugate, FP32 storage with FP64 arithmetic

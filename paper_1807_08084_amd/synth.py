@@ -200,7 +200,7 @@ def wishart_sigma0(z_planes: np.ndarray, ridge: float = 0.1) -> np.ndarray:
 
 
 # ---------------------------------------------------------------- workloads
-# The five workloads: shapes, looks, region grids and eigenvalue ranges.
+# The workloads: shapes, looks, region grids and eigenvalue ranges.
 
 def workload_small(seed=0):
     """256x256, N=4, 2x2 regions, lam in [1e-2, 1]."""
@@ -210,6 +210,11 @@ def workload_small(seed=0):
 def workload_scale(seed=1, rows=None, with_looks=False):
     """4096x4096, N=4, 4x4 regions, lam in [1e-3, 1]."""
     return make_image(4096, 4096, 4, (4, 4), (1e-3, 1.0), seed, rows=rows, with_looks=with_looks)
+
+
+def workload_scale8192(seed=5, rows=None):
+    """8192x8192 with the 4096x4096 recipe: N=4, 4x4 regions, lam in [1e-3, 1]."""
+    return make_image(8192, 8192, 4, (4, 4), (1e-3, 1.0), seed, rows=rows)
 
 
 def workload_boxcar(seed=4, side=4096):
