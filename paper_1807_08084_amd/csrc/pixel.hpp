@@ -36,8 +36,16 @@ PX_HD double log_(double x) { return log(x); }
 template <class T> PX_HD bool finite_(T x) { return __builtin_isfinite(x); }
 
 template <class T> struct Eps;
-template <> struct Eps<float> { static constexpr double u = 5.9604644775390625e-08; };   // 2^-24
-template <> struct Eps<double> { static constexpr double u = 1.1102230246251565e-16; };  // 2^-53
+// u: unit roundoff; eta: smallest normal number, a bound on the absolute
+// error one operation can add when its result is subnormal (or flushed).
+template <> struct Eps<float> {
+  static constexpr double u = 5.9604644775390625e-08;   // 2^-24
+  static constexpr double eta = 1.1754943508222875e-38;  // 2^-126
+};
+template <> struct Eps<double> {
+  static constexpr double u = 1.1102230246251565e-16;   // 2^-53
+  static constexpr double eta = 2.2250738585072014e-308;  // 2^-1022
+};
 
 // ---------------------------------------------------------------------------
 // Alg. 2 (Section 3.1), evaluated directly.
@@ -129,9 +137,14 @@ PX_HD void two_sum(T a, T b, T& s, T& e) {
   e = (a - (s - bb)) + (b - bb);
 }
 
-// Dot2 of (x1 y1 + x2 y2 + x3 y3); also returns sum|x_k y_k| (rounded).
+// Dot2 of (x1 y1 + x2 y2 + x3 y3).  The products' rounding errors (FMA)
+// and the additions' (TwoSum) are exact; only the two rounded additions
+// that gather them into the low word, t = q + r and s = s + t, lose
+// anything, each at most u times its rounded result (round to nearest).
+// rerr returns their running error sum |t1| + |s1| + |t2| + |s2|, so that
+// |hi + lo - exact| <= u * rerr.
 template <class T>
-PX_HD DW<T> dot3(T x1, T y1, T x2, T y2, T x3, T y3, T& mag) {
+PX_HD DW<T> dot3(T x1, T y1, T x2, T y2, T x3, T y3, T& rerr) {
 #if defined(__clang__)
 #pragma clang fp contract(off)
 #endif
@@ -140,42 +153,51 @@ PX_HD DW<T> dot3(T x1, T y1, T x2, T y2, T x3, T y3, T& mag) {
   T h = x2 * y2;
   T r = fma_(x2, y2, -h);
   T q;
-  mag = abs_(p) + abs_(h);
   two_sum(p, h, p, q);
-  s = s + (q + r);
+  T t = q + r;
+  s = s + t;
+  rerr = abs_(t) + abs_(s);
   h = x3 * y3;
   r = fma_(x3, y3, -h);
-  mag = mag + abs_(h);
   two_sum(p, h, p, q);
-  s = s + (q + r);
+  t = q + r;
+  s = s + t;
+  rerr = rerr + (abs_(t) + abs_(s));
   return DW<T>{p, s};
 }
 
 template <class T>
-PX_HD void cofactors_comp(const T z[9], DW<T> c[9], T mag[9]) {
+PX_HD void cofactors_comp(const T z[9], DW<T> c[9], T rerr[9]) {
   const T a = z[0], d = z[1], f = z[2], br = z[3], bi = z[4], cr = z[5], ci = z[6], er = z[7], ei = z[8];
-  c[0] = dot3(d, f, -er, er, -ei, ei, mag[0]);
-  c[1] = dot3(a, f, -cr, cr, -ci, ci, mag[1]);
-  c[2] = dot3(a, d, -br, br, -bi, bi, mag[2]);
-  c[3] = dot3(cr, er, ci, ei, -br, f, mag[3]);
-  c[4] = dot3(ci, er, -cr, ei, -bi, f, mag[4]);
-  c[5] = dot3(br, er, -bi, ei, -cr, d, mag[5]);
-  c[6] = dot3(br, ei, bi, er, -ci, d, mag[6]);
-  c[7] = dot3(cr, br, ci, bi, -a, er, mag[7]);
-  c[8] = dot3(ci, br, -cr, bi, -a, ei, mag[8]);
+  c[0] = dot3(d, f, -er, er, -ei, ei, rerr[0]);
+  c[1] = dot3(a, f, -cr, cr, -ci, ci, rerr[1]);
+  c[2] = dot3(a, d, -br, br, -bi, bi, rerr[2]);
+  c[3] = dot3(cr, er, ci, ei, -br, f, rerr[3]);
+  c[4] = dot3(ci, er, -cr, ei, -bi, f, rerr[4]);
+  c[5] = dot3(br, er, -bi, ei, -cr, d, rerr[5]);
+  c[6] = dot3(br, ei, bi, er, -ci, d, rerr[6]);
+  c[7] = dot3(cr, br, ci, bi, -a, er, rerr[7]);
+  c[8] = dot3(ci, br, -cr, bi, -a, ei, rerr[8]);
 }
 
-// Compensated determinant from the row-0 expansion; returns the rounded det
-// and the a-posteriori bound E >= |det_returned - det(A)| where
-//   E = (1 + 64u) [ u|det| + 64u^2 sum|x_i hi_i| + 40u^2 sum|x_i| S_i ],
-// x = (a, Re b, Im b, Re c, Im c), S_i = sum|products| of cofactor i.
-// Constants: the five-term Dot2 contributes gamma_5^2 + gamma_5 gamma_6
-// (<= 56u^2) on sum|x_i hi_i|; the low words (|lo_i| <= gamma_4 S_i) added
-// with gamma_6 give 24u^2 on sum|x_i| S_i, the cofactors' own Dot2 errors
-// gamma_3^2 (<= 9u^2) on the same sum; the final rounding u|det|.  All
-// rounded up, with a (1 + 64u) margin for evaluating E itself.
+// Compensated determinant from the row-0 expansion, x = (a, Re b, Im b,
+// Re c, Im c): the Dot2 sum of the five products x_i hi_i, then the five
+// x_i lo_i added into its low word.  Returns the rounded det and the
+// a-posteriori bound E >= |det_returned - det(A)| from a running error
+// analysis: every rounded addition into the low word (t = q + r, s = s + t,
+// and each s = fma(x_i, lo_i, s)) is off by at most u times its rounded
+// result, R being the sum of those results' magnitudes; the cofactors are
+// off by at most u rerr_i each, C = sum |x_i| rerr_i; the final rounding
+// adds u |det|.  Where results are subnormal (or flushed to zero) the
+// error-free transformations stop being exact: each of the at most 48
+// operations of the determinant and 22 of each cofactor can then add eta,
+// the smallest normal number, which the term 64 eta (1 + sum |x_i|) covers:
+//   E = (1 + 64u) [u (|det| + R + C) + 64 eta (1 + sum |x_i|)],
+// the (1 + 64u) covering the rounding of R, C and E themselves.  With
+// entries far below 1e-10 in FP32 that term exceeds 1e-6 |det| and the
+// pixel is recomputed in FP64, where nothing underflows.
 template <class T>
-PX_HD T det_comp(const T z[9], const DW<T> c[9], const T mag[9], T& bound) {
+PX_HD T det_comp(const T z[9], const DW<T> c[9], const T rerr[9], T& bound) {
 #if defined(__clang__)
 #pragma clang fp contract(off)
 #endif
@@ -183,24 +205,30 @@ PX_HD T det_comp(const T z[9], const DW<T> c[9], const T mag[9], T& bound) {
   const int idx[5] = {0, 3, 4, 5, 6};
   T p = x[0] * c[0].hi;
   T s = fma_(x[0], c[0].hi, -p);
-  T A = abs_(p);
-  T C = abs_(x[0]) * mag[0];
+  T R = T(0);
+  T C = abs_(x[0]) * rerr[0];
+  T X = abs_(x[0]);
 #pragma unroll
   for (int i = 1; i < 5; ++i) {
     const T h = x[i] * c[idx[i]].hi;
     const T r = fma_(x[i], c[idx[i]].hi, -h);
     T q;
-    A = A + abs_(h);
-    C = fma_(abs_(x[i]), mag[idx[i]], C);
+    C = fma_(abs_(x[i]), rerr[idx[i]], C);
+    X = X + abs_(x[i]);
     two_sum(p, h, p, q);
-    s = s + (q + r);
+    const T t = q + r;
+    s = s + t;
+    R = R + (abs_(t) + abs_(s));
   }
 #pragma unroll
-  for (int i = 0; i < 5; ++i) s = fma_(x[i], c[idx[i]].lo, s);
+  for (int i = 0; i < 5; ++i) {
+    s = fma_(x[i], c[idx[i]].lo, s);
+    R = R + abs_(s);
+  }
   const T det = p + s;
   constexpr T u = (T)Eps<T>::u;
-  constexpr T u2 = (T)(Eps<T>::u * Eps<T>::u);
-  bound = (T(1) + T(64) * u) * (u * abs_(det) + (T(64) * u2) * A + (T(40) * u2) * C);
+  constexpr T eta64 = (T)(64.0 * Eps<T>::eta);
+  bound = (T(1) + T(64) * u) * fma_(eta64, T(1) + X, u * ((abs_(det) + R) + C));
   return det;
 }
 
@@ -216,9 +244,9 @@ PX_HD void scale_comp(const DW<T> c[9], T t, T x[9]) {
 // Compensated FP64 (no reroute: FP64 is the widest type on the path).
 PX_HD int adjugate_comp(const double z[9], double x[9], double& det) {
   DW<double> c[9];
-  double mag[9], bound;
-  cofactors_comp(z, c, mag);
-  det = det_comp(z, c, mag, bound);
+  double rerr[9], bound;
+  cofactors_comp(z, c, rerr);
+  det = det_comp(z, c, rerr, bound);
   const double t = 1.0 / det;
   scale_comp(c, t, x);
   return classify(det, t, z[0], c[2].hi + c[2].lo);
@@ -237,9 +265,9 @@ constexpr float REROUTE_REL = 1e-6f;
 // pixel is accepted, false when it must be recomputed.
 PX_HD bool adjugate_comp_try(const float z[9], float x[9], float& det, float* bound_out = nullptr) {
   DW<float> c[9];
-  float mag[9], bound;
-  cofactors_comp(z, c, mag);
-  det = det_comp(z, c, mag, bound);
+  float rerr[9], bound;
+  cofactors_comp(z, c, rerr);
+  det = det_comp(z, c, rerr, bound);
   if (bound_out) *bound_out = bound;
   const float t = 1.0f / det;
   const bool ok = det > 0.0f && finite_(det) && finite_(t) && !(bound > REROUTE_REL * det) && z[0] > 0.0f &&
@@ -284,10 +312,10 @@ PX_HD int adjugate_comp_reroute(const float z[9], float x[9], float& det) {
   int st;
   {
     DW<double> c[9];
-    const double no_mag[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // the bound is not used here
+    const double no_rerr[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // the bound is not used here
     double bound;
     cofactors_widened(zd, c);
-    dd = det_comp(zd, c, no_mag, bound);
+    dd = det_comp(zd, c, no_rerr, bound);
     const double t = 1.0 / dd;
     scale_comp(c, t, xd);
     st = classify(dd, t, zd[0], c[2].hi + c[2].lo);

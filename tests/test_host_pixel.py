@@ -66,6 +66,28 @@ def test_f32_compensated_reroute_and_bound():
     assert np.all(st[pd & (k < 1e7)] <= 1)
 
 
+def test_f32_bound_covers_tiny_entries():
+    """Near rank-2 matrices scaled by 10^s, s uniform in [-12, 12]: below about
+    1e-10 the FP32 products underflow and the error-free transformations stop
+    being exact; the bound's underflow term must still cover the true error of
+    every kept pixel (such pixels are recomputed in FP64 instead)."""
+    rng = np.random.default_rng(34)
+    m = 40000
+    U = synth.haar_unitary(rng, m)
+    scale = 10.0 ** rng.uniform(-12, 12, m)
+    eig = np.stack([np.ones(m), 10.0 ** -rng.uniform(0, 3, m), 10.0 ** -rng.uniform(5, 12, m)], 1) * scale[:, None]
+    z32 = synth.pack(np.einsum("mij,mj,mkj->mik", U, eig, np.conj(U))).astype(np.float32)
+    inv, det, st, bound = pixel.adjugate_comp_f32(z32)
+    (ih, il), (dh, dl) = oracle.ge128(z32.astype(np.float64))
+    kept = st == 0
+    err = np.abs((det.astype(np.float64) - dh) - dl)
+    assert kept.sum() > 5000
+    assert np.all(err[kept] <= bound[kept].astype(np.float64))
+    assert np.all(err[kept] <= 1e-6 * np.abs(dh[kept]))
+    # the tiniest matrices are all recomputed (or not positive definite)
+    assert np.all(st[scale < 1e-11] != 0)
+
+
 def test_indefinite_with_positive_determinant_is_not_pd():
     """Eigenvalues (-l1, -l2, l3): det > 0 but not positive definite; the
     leading-minor test flags every one (the oracle's pivot signs agree)."""
