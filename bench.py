@@ -5,11 +5,15 @@ eigenvalues log-uniform in [1e-3, 1], seed 1; FP32 planes (36 B in, 40 B out
 per pixel).  One step = one polsar_inv_det call over the whole image with the
 adjugate method, compensated FP32 arithmetic and FP64 recompute of flagged
 pixels, data resident in HBM.  Beside it the same image is timed with the
-Cholesky form and other precisions, the Wishart forward+backward and a plane
-copy of the same byte count (measured bandwidth ceiling); the CPU oracle is
-timed on the host.  Prints one JSON line.
+Cholesky form and other precisions, the Wishart forward+backward, the fused
+multilook front ends, the nonlocal-means filter, the out-of-core streamer and
+a plane copy of the same byte count (its launch swept: the measured bandwidth
+ceiling); the CPU oracle is timed on the host.  Then (unless --no-rows or
+--no-workloads) the other workloads: an 8192x8192 image of the same recipe, the 8192x8192
+recompute-heavy precision image (default and autotuned launch), the
+2048x2048 Wishart image and the 64-image batch.  Prints one JSON line.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-rows]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-rows] [--no-workloads]
 """
 from __future__ import annotations
 
@@ -249,14 +253,17 @@ def main():
     ap.add_argument("--no-rows", action="store_true")
     ap.add_argument("--tune", action="store_true", help="autotune the launch before timing")
     ap.add_argument("--workloads", action="store_true",
-                    help="also time the precision (8192^2), Wishart (2048^2) and 64-image batch workloads")
+                    help="time the other workloads too (the default unless --no-rows or --no-workloads)")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the 8192^2, precision, Wishart 2048^2 and 64-image batch workloads")
     ap.add_argument("--probe", action="store_true",
                     help="after the timed steps, run a one-plane copy of the same pixel count "
                          "(known bytes: calibrates the HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(every pixel is independent: see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
+              "(every pixel is independent: an image shards by rows across GPUs, and only the "
+              "Wishart loss, one FP64 scalar, would need an all-reduce)", file=sys.stderr)
         sys.exit(2)
 
     from paper_1807_08084_amd import synth
@@ -435,7 +442,7 @@ def main():
             "f32_equal_accuracy_vs_cholesky_wide": round(rows["cholesky_wide_f32"]["ms"] / adj, 3),
             "f64_plain": round(rows["cholesky_plain_f64"]["ms"] / rows["adjugate_plain_f64"]["ms"], 3),
             "paper_context": "about 2.2x on a GeForce 940M, OpenCL (Table 2)"}
-    if args.workloads:
+    if args.workloads or not (args.no_rows or args.no_workloads):
         out["workloads"] = other_workloads(torch, ops, dev, max(10, args.steps // 4))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(z64.astype(np.float32).astype(np.float64), n_px)

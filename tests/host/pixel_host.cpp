@@ -1,6 +1,6 @@
 // Host build of the kernels' per-pixel compensated arithmetic (pixel.hpp),
 // for tests: the reroute bound is validated on the CPU and device results
-// are compared bitwise against this build.  The compensated functions use
+// are compared bitwise against these host results.  The compensated functions use
 // explicit FMAs only, so with contraction off the host and device evaluate
 // identical operation sequences.
 // Build: g++ -O2 -std=c++17 -fPIC -shared -fopenmp -ffp-contract=off
