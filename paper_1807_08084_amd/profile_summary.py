@@ -2,6 +2,7 @@
 
     python -m paper_1807_08084_amd.profile_summary trace <kt_results.db> <out.txt> "<command>"
     python -m paper_1807_08084_amd.profile_summary traffic <fetch.db> <write.db> <out.txt> "<commands>"
+    python -m paper_1807_08084_amd.profile_summary counters <pmc.db> <out.txt> "<command>"
 
 ``trace`` lists each kernel's calls and mean duration (the --kernel-trace
 --stats view).  ``traffic`` turns per-dispatch FETCH_SIZE / WRITE_SIZE (KiB)
@@ -84,8 +85,36 @@ def traffic(fetch_db: str, write_db: str, out: str, command: str, n_px: int = 40
     print(open(out).read())
 
 
+def counters(db: str, out: str, command: str, n_px: int = 4096 * 4096) -> None:
+    """Mean of each counter per dispatch, by kernel and grid size, and the
+    VALU lane-instructions per pixel (SQ_INSTS_VALU x 64 / n_px) for
+    dispatches that cover an n_px-pixel image."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select kernel_name, grid_size, counter_name, value from counters_collection").fetchall()
+    agg = {}
+    for k, g, cn, v in rows:
+        agg.setdefault((short(k), g), {}).setdefault(cn, []).append(v)
+    names = sorted({cn for d in agg.values() for cn in d})
+    with open(out, "w") as fh:
+        fh.write(f"# rocprofv3 --pmc summary: mean per dispatch\n# command: {command}\n")
+        fh.write(f"# source_hash = {source_hash()}\n")
+        fh.write(f"# valu_per_px = SQ_INSTS_VALU * 64 / {n_px} (meaningful where the dispatch covers the image)\n")
+        fh.write(f"{'kernel':44s} {'grid':>10s} {'calls':>5s} " + " ".join(f"{n:>15s}" for n in names)
+                 + f" {'valu_per_px':>11s}\n")
+        for key in sorted(agg, key=lambda t: (t[0], t[1])):
+            d = agg[key]
+            calls = max(len(v) for v in d.values())
+            means = [statistics.mean(d[n]) if n in d else float("nan") for n in names]
+            vpp = statistics.mean(d["SQ_INSTS_VALU"]) * 64 / n_px if "SQ_INSTS_VALU" in d else float("nan")
+            fh.write(f"{key[0][:44]:44s} {key[1]:10d} {calls:5d} " + " ".join(f"{m:15.0f}" for m in means)
+                     + f" {vpp:11.1f}\n")
+    print(open(out).read())
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "counters":
+        counters(sys.argv[2], sys.argv[3], sys.argv[4])
     else:
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
