@@ -343,6 +343,12 @@ PX_HD int adjugate_comp(const float z[9], float x[9], float& det, float* bound_o
 //   a += |S_HH|^2, d += |S_HV|^2, f += |S_VV|^2,
 //   b += S_HH conj(S_HV), c += S_HH conj(S_VV), e += S_HV conj(S_VV).
 // s = (Re S_HH, Im S_HH, Re S_HV, Im S_HV, Re S_VV, Im S_VV).
+// look_accumulate forms each component's two-product sum first and adds it
+// (three operations, a short dependency chain from look to look);
+// look_accumulate_chained adds each real product with one FMA (two
+// operations, twice the chain).  The first suits the per-pixel multilook
+// (few looks per lane, latency-bound), the second the boxcar (many looks
+// per row sum, bound by VALU issue).  Both round once per addition.
 // ---------------------------------------------------------------------------
 template <class T>
 PX_HD void look_accumulate(const T s[6], double acc[9]) {
@@ -356,6 +362,20 @@ PX_HD void look_accumulate(const T s[6], double acc[9]) {
   acc[6] += hi * wr - hr * wi;
   acc[7] += vr * wr + vi * wi;
   acc[8] += vi * wr - vr * wi;
+}
+
+template <class T>
+PX_HD void look_accumulate_chained(const T s[6], double acc[9]) {
+  const double hr = s[0], hi = s[1], vr = s[2], vi = s[3], wr = s[4], wi = s[5];
+  acc[0] = fma_(hi, hi, fma_(hr, hr, acc[0]));
+  acc[1] = fma_(vi, vi, fma_(vr, vr, acc[1]));
+  acc[2] = fma_(wi, wi, fma_(wr, wr, acc[2]));
+  acc[3] = fma_(hi, vi, fma_(hr, vr, acc[3]));
+  acc[4] = fma_(-hr, vi, fma_(hi, vr, acc[4]));
+  acc[5] = fma_(hi, wi, fma_(hr, wr, acc[5]));
+  acc[6] = fma_(-hr, wi, fma_(hi, wr, acc[6]));
+  acc[7] = fma_(vi, wi, fma_(vr, wr, acc[7]));
+  acc[8] = fma_(-vr, wi, fma_(vi, wr, acc[8]));
 }
 
 // ---------------------------------------------------------------------------

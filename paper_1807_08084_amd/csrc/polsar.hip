@@ -231,17 +231,18 @@ __global__ __launch_bounds__(256) void k_multilook(MultilookArgs a) {
 // A block (one wave) owns BOX_TW output columns of a strip of BOX_STRIP
 // rows and walks down it one input row at a time: the row's single-look
 // pixels (with an R-pixel halo each side, zeros outside the image, which add
-// nothing) are staged in LDS, double-buffered, while the next row is being
-// loaded; each lane forms the sum of its 2R+1 horizontal neighbours' outer
-// products in FP64 (exact products for FP32 input) and keeps the last 2R+1
-// such row sums in registers, oldest first (shifted down one slot per row,
-// so every index is fixed at compile time and the loop body, with its
+// nothing) are staged in LDS in FP64, double-buffered, while the next row is
+// being loaded; each lane forms the sum of its 2R+1 horizontal neighbours'
+// outer products in FP64 (exact products for FP32 input) and keeps the last
+// 2R+1 such row sums in registers, oldest first (shifted down one slot per
+// row, so every index is fixed at compile time and the loop body, with its
 // inverse, exists once).  Once a lane holds the rows of its output's window
-// it adds them in ascending row order, divides by the clipped window size,
-// rounds Z to the storage type (optionally stores it) and inverts it with
-// the per-pixel function of the per-call kernel.  Each row sum is formed
-// once per strip, so the work per output is (2R+1) outer products and 2R+1
-// additions of nine components, plus the halo rows of the strip.
+// it adds them in ascending row order, scales by the reciprocal of the
+// clipped window size (within an FP64 ulp of the quotient), rounds Z to the
+// storage type (optionally stores it) and inverts it with the per-pixel
+// function of the per-call kernel.  Each row sum is formed once per strip,
+// so the work per output is (2R+1) outer products and 2R+1 additions of
+// nine components, plus the halo rows of the strip.
 constexpr int BOX_TW = 64, BOX_STRIP = 32, BOX_MAX_R = 3;
 
 struct BoxArgs {
@@ -262,7 +263,7 @@ template <class T, int OP, int R>
 __global__ __launch_bounds__(BOX_TW) void k_boxcar(BoxArgs a) {
   constexpr int K = 2 * R + 1, SW = BOX_TW + 2 * R;
   constexpr int P = (SW + BOX_TW - 1) / BOX_TW;  // staged pixels per lane and row
-  __shared__ T row[2][6][SW];
+  __shared__ double row[2][6][SW];  // staged in FP64 (exact for FP32 input)
   const T* __restrict__ S = (const T*)a.s;
   const int lane = threadIdx.x;
   const int64_t bx = (int64_t)blockIdx.x % a.nbx, by = (int64_t)blockIdx.x / a.nbx;
@@ -301,7 +302,7 @@ __global__ __launch_bounds__(BOX_TW) void k_boxcar(BoxArgs a) {
       const int col = lane + p * BOX_TW;
       if (col < SW)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) row[b][k][col] = pre[p][k];
+        for (int k = 0; k < 6; ++k) row[b][k][col] = (double)pre[p][k];
     }
     __syncthreads();
     if (y + 1 <= y_last) load_row(y + 1, pre);  // in flight while this row is summed
@@ -313,10 +314,10 @@ __global__ __launch_bounds__(BOX_TW) void k_boxcar(BoxArgs a) {
     for (int c = 0; c < 9; ++c) ring[K - 1][c] = 0.0;
 #pragma unroll
     for (int dx = 0; dx < K; ++dx) {
-      T s6[6];
+      double s6[6];
 #pragma unroll
       for (int k = 0; k < 6; ++k) s6[k] = row[b][k][lane + dx];
-      px::look_accumulate(s6, ring[K - 1]);
+      px::look_accumulate_chained(s6, ring[K - 1]);
     }
     // output row y - R, whose window rows y - 2R .. y the ring now holds
     const int64_t yo = y - R;
@@ -327,10 +328,10 @@ __global__ __launch_bounds__(BOX_TW) void k_boxcar(BoxArgs a) {
 #pragma unroll
         for (int c = 0; c < 9; ++c) acc[c] += ring[m][c];
       const int64_t rows = (yo + R < a.H ? yo + R : a.H - 1) - (yo - R > 0 ? yo - R : 0) + 1;
-      const double cnt = (double)(rows * cols);
+      const double rcp = 1.0 / (double)(rows * cols);
       T zz[9], xx[9], dt;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) zz[c] = (T)(acc[c] / cnt);
+      for (int c = 0; c < 9; ++c) zz[c] = (T)(acc[c] * rcp);
       const int64_t i = yo * a.W + gx;
       if (a.z)
 #pragma unroll
