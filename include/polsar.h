@@ -62,7 +62,9 @@ typedef enum { POLSAR_ADJUGATE = 0, POLSAR_CHOLESKY = 1 } polsar_method;
  *   PLAIN        the algorithm in the storage type.
  *   COMPENSATED  ADJUGATE: Dot2-compensated cofactors and determinant (FMA
  *                error-free products and sums); in F32, pixels whose
- *                a-posteriori determinant error bound exceeds 1e-6 relative,
+ *                a-posteriori determinant error bound (a running error
+ *                analysis of that evaluation, subnormal results included)
+ *                exceeds 1e-6 relative,
  *                or whose det is not positive or not finite, are recomputed
  *                by the compensated F64 path (status POLSAR_PX_REROUTED).
  *                CHOLESKY (F32 only): F32, pixels whose pivots fail
