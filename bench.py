@@ -90,6 +90,31 @@ def time_calls(fn, steps: int, warmup: int, torch, min_warm_seconds: float = 0.0
     return e0.elapsed_time(e1) / steps  # ms per call
 
 
+def launch_spread(fn, n: int, torch) -> dict:
+    """n single launches, each between its own pair of events: min, median,
+    mean, max and standard deviation in ms."""
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    per = np.array([a.elapsed_time(b) for a, b in evs])
+    return {"n": int(per.size), "min": round(float(per.min()), 4), "median": round(float(np.median(per)), 4),
+            "mean": round(float(per.mean()), 4), "max": round(float(per.max()), 4),
+            "std": round(float(per.std()), 4)}
+
+
+# Table 2 of the paper (ms over 1000 replicates on a GeForce 940M, OpenCL,
+# precision not stated): context for the paper-shaped rows, not a target.
+PAPER_TABLE2_MS = {
+    "simulated_5469354": {"adjugate": {"min": 223.06, "mean": 231.51, "max": 273.08, "std": 6.11},
+                          "cholesky": {"min": 498.89, "mean": 507.54, "max": 556.79, "std": 9.34}},
+    "airsar_450x600": {"adjugate": {"min": 11.18, "mean": 12.98, "max": 28.59, "std": 1.44},
+                       "cholesky": {"min": 24.68, "mean": 28.35, "max": 62.60, "std": 2.55}},
+}
+
+
 def cpu_baseline(z64: np.ndarray, n_px: int, min_seconds: float = 10.0):
     import oracle
     threads = oracle.threads()
@@ -241,6 +266,25 @@ def other_workloads(torch, ops, dev, steps):
                               "graph_GB_s": round(148 * n / g_ms / 1e6, 1),
                               "ops": "inverse+det of Z, Wishart fwd+bwd of S against Z (FP32 compensated)"}
     plan.close()
+    # the paper's Table 2 shapes: 5,469,354 simulated M M^H matrices and a
+    # 450 x 600 image, both forms, single launches like the paper's replicates
+    shapes = (("simulated_5469354", synth.workload_paper_simulated()),
+              ("airsar_450x600", synth.workload_airsar_standin().planes.reshape(9, -1)))
+    paper = {}
+    for name, planes in shapes:
+        n = planes.shape[1]
+        rec = {"pixels": n, "paper_ms": PAPER_TABLE2_MS[name]}
+        for dt, tn in ((torch.float32, "f32"), (torch.float64, "f64")):
+            z = ops.upload_planes(planes, dt, dev)
+            o = ops.empty_planes(10, n, dt, dev)
+            for method, prec in (("adjugate", "plain"), ("cholesky", "plain"), ("adjugate", "compensated")):
+                f = lambda: ops.inv_det(z, method, prec, inv=o[:9], det=o[9])
+                warm(f, 10, torch)
+                rec[f"{method}_{prec}_{tn}_ms"] = launch_spread(f, 1000, torch)
+            del z, o
+        paper[name] = rec
+    res["paper_table2_shapes"] = paper
+    print(f"# paper-shaped workloads done", file=sys.stderr, flush=True)
     return res
 
 
@@ -290,20 +334,9 @@ def main():
 
     warm_done = warm(step, args.warmup, torch, min_seconds=0.5)
     ms = time_calls(step, args.steps, 0, torch)
-    # the spread of single launches, each between its own pair of events
-    # (after the timed region; not part of the value)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    for a, b in evs:
-        a.record()
-        step()
-        b.record()
-    torch.cuda.synchronize()
-    per = np.array([a.elapsed_time(b) for a, b in evs])
-    launch_stats = {"n": int(per.size), "min": round(float(per.min()), 4),
-                    "median": round(float(np.median(per)), 4), "mean": round(float(per.mean()), 4),
-                    "max": round(float(per.max()), 4), "std": round(float(per.std()), 4),
-                    "gpx_s_at_median": round(n_px / float(np.median(per)) / 1e6, 3)}
+    # the spread of single launches (after the timed region; not part of the value)
+    launch_stats = launch_spread(step, args.steps, torch)
+    launch_stats["gpx_s_at_median"] = round(n_px / launch_stats["median"] / 1e6, 3)
     if args.probe:
         src1 = z32[0:1]
         dst1 = ops.empty_planes(1, n_px, torch.float32, dev)

@@ -248,3 +248,35 @@ def workload_batch(seed=7, count=64, max_images=None):
     kids = np.random.SeedSequence(seed).spawn(count)
     sel = range(count if max_images is None else min(count, max_images))
     return [make_image(shapes[i][0], shapes[i][1], shapes[i][2], (2, 4), (1e-2, 1.0), kids[i]) for i in sel]
+
+
+# ------------------------------------------------------------ the paper's shapes
+# Stand-ins for the inputs of the paper's timing experiment (Section 4 and
+# Table 2), for quoting beside its numbers: simulated matrices M M^H with the
+# real and imaginary parts of the 3x3 M independent uniform on [-1, 1]
+# (5,469,354 of them), and a 450 x 600 image in place of the AIRSAR scene
+# (the small workload's recipe at that shape; the scene itself is not here).
+PAPER_SIMULATED_COUNT = 5_469_354
+
+
+def workload_paper_simulated(seed=6, count=PAPER_SIMULATED_COUNT) -> np.ndarray:
+    """(9, count) FP64 planes of M M^H, drawn in fixed chunks of CHUNK
+    matrices, one SeedSequence child each."""
+    out = np.empty((9, count))
+    kids = np.random.SeedSequence(seed).spawn((count + CHUNK - 1) // CHUNK)
+
+    def chunk(k: int) -> None:
+        c0, c1 = k * CHUNK, min(count, (k + 1) * CHUNK)
+        rng = np.random.default_rng(kids[k])
+        m = rng.uniform(-1.0, 1.0, (c1 - c0, 3, 3)) + 1j * rng.uniform(-1.0, 1.0, (c1 - c0, 3, 3))
+        out[:, c0:c1] = pack(m @ np.conj(np.transpose(m, (0, 2, 1))))
+
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(_workers()) as ex:
+        list(ex.map(chunk, range(len(kids))))
+    return out
+
+
+def workload_airsar_standin(seed=8):
+    """450 x 600, N=4, 2x2 regions, lam in [1e-2, 1]."""
+    return make_image(450, 600, 4, (2, 2), (1e-2, 1.0), seed)

@@ -70,3 +70,19 @@ def test_wishart_sigma0():
     for k in range(3):
         assert np.allclose(s[k], z[k] + 0.1 * tr / 3)
     assert np.array_equal(s[3:], z[3:])
+
+
+def test_paper_shaped_stand_ins():
+    """M M^H with Re/Im(M) uniform on [-1, 1]: Hermitian positive definite,
+    E[M M^H] = (2/3) 3 I = 2 I; chunks identical whatever the count; the
+    450 x 600 image has the small recipe's planes at that shape."""
+    p = synth.workload_paper_simulated(count=300000)
+    z = synth.unpack(p)
+    assert np.allclose(z, np.conj(np.transpose(z, (0, 2, 1))))
+    assert np.all(np.linalg.eigvalsh(z[:20000]) > 0)
+    mean = z.mean(axis=0)
+    assert np.allclose(mean, 2.0 * np.eye(3), atol=0.02)
+    q = synth.workload_paper_simulated(count=synth.CHUNK + 5)
+    assert np.array_equal(q[:, :synth.CHUNK], p[:, :synth.CHUNK])
+    a = synth.workload_airsar_standin()
+    assert a.planes.shape == (9, 450, 600)
