@@ -3,6 +3,7 @@
     python -m paper_1807_08084_amd.profile_summary trace <kt_results.db> <out.txt> "<command>"
     python -m paper_1807_08084_amd.profile_summary traffic <fetch.db> <write.db> <out.txt> "<commands>"
     python -m paper_1807_08084_amd.profile_summary counters <pmc.db> <out.txt> "<command>"
+    python -m paper_1807_08084_amd.profile_summary traffic_rows <fetch.db> <write.db> <out.txt> "<commands>"
 
 ``trace`` lists each kernel's calls and mean duration (the --kernel-trace
 --stats view).  ``traffic`` turns per-dispatch FETCH_SIZE / WRITE_SIZE (KiB)
@@ -85,6 +86,48 @@ def traffic(fetch_db: str, write_db: str, out: str, command: str, n_px: int = 40
     print(open(out).read())
 
 
+# Kernels of the bench rows on the 4096x4096 image and their algorithmic
+# bytes per pixel (read, written).
+ROW_KERNELS = [
+    ("k_inv_det<float, 1, 2, 1, true>", "FP32 compensated adjugate", 36, 40),
+    ("k_inv_det<double, 1, 2, 1, true>", "FP64 compensated adjugate", 72, 80),
+    ("k_inv_det<float, 3, 2, 1, true>", "FP32 plain Cholesky", 36, 40),
+    ("k_wishart<float, 4, 1, true>", "FP32 Wishart fwd+bwd", 72, 36),
+    ("k_wishart<double, 1, 1, true>", "FP64 Wishart fwd+bwd", 144, 72),
+    ("k_boxcar<float, 1, 1>", "boxcar 3x3 (halo rows: +2/32 of the reads)", 24, 40),
+    ("k_boxcar<float, 1, 3>", "boxcar 7x7 (halo rows: +6/32 of the reads)", 24, 40),
+]
+
+
+def traffic_rows(fetch_db: str, write_db: str, out: str, command: str, n_px: int = 4096 * 4096) -> None:
+    """HBM bytes per pixel of the bench rows' kernels (FETCH_SIZE / WRITE_SIZE
+    per dispatch, scaled by the one-plane copy probe) against their
+    algorithmic bytes."""
+    f = _counter(fetch_db, "FETCH_SIZE")
+    w = _counter(write_db, "WRITE_SIZE")
+
+    def one_plane_copy(k):
+        args = k[k.find("<") + 1:k.rfind(">")].split(", ")
+        return k.startswith("k_copy<float,") and args[2:4] == ["1", "1"]
+    probe = next(k for k in f if one_plane_copy(k))
+    f_scale = 4 * n_px / (f[probe] * 1024)
+    w_scale = 4 * n_px / (w[probe] * 1024)
+    with open(out, "w") as fh:
+        fh.write("# HBM traffic per pixel of the bench rows' kernels, 4096x4096 image\n")
+        fh.write(f"# command: {command}\n")
+        fh.write(f"# source_hash = {source_hash()}\n")
+        fh.write(f"# scales from the one-plane copy probe: FETCH_SIZE x{f_scale:.5f}, WRITE_SIZE x{w_scale:.5f}\n")
+        fh.write(f"{'kernel':36s} {'read B/px':>10s} {'alg':>5s} {'ratio':>7s} {'write B/px':>11s} {'alg':>5s} "
+                 f"{'ratio':>7s}  what\n")
+        for name, what, ar, aw in ROW_KERNELS:
+            if name not in f or name not in w:
+                continue
+            rd = f[name] * 1024 * f_scale / n_px
+            wr = w[name] * 1024 * w_scale / n_px
+            fh.write(f"{name:36s} {rd:10.2f} {ar:5d} {rd / ar:7.4f} {wr:11.2f} {aw:5d} {wr / aw:7.4f}  {what}\n")
+    print(open(out).read())
+
+
 def counters(db: str, out: str, command: str, n_px: int = 4096 * 4096) -> None:
     """Mean of each counter per dispatch, by kernel and grid size, and the
     VALU lane-instructions per pixel (SQ_INSTS_VALU x 64 / n_px) for
@@ -116,5 +159,7 @@ if __name__ == "__main__":
         trace(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "counters":
         counters(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "traffic_rows":
+        traffic_rows(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
     else:
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
