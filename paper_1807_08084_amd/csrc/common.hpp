@@ -246,6 +246,18 @@ __device__ __forceinline__ double block_sum(double v) {
   return s;
 }
 
+// Tile of block b in a grid of g blocks.  The hardware deals the blocks of
+// a grid out to MI355X's eight XCDs in turn (block b to XCD b mod 8), and
+// each XCD has its own L2; this mapping gives the blocks of one XCD a
+// contiguous run of tiles, so that neighbouring tiles, which read the same
+// halo, meet in the same L2.  A bijection on [0, g): XCD k takes
+// g / 8 + (k < g mod 8) tiles, starting where XCD k - 1's run ends.
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned g) {
+  constexpr unsigned NX = 8;
+  const unsigned q = g / NX, r = g % NX, k = b % NX, j = b / NX;
+  return k * q + (k < r ? k : r) + j;
+}
+
 // Fixed-order sum of p[0 .. count) by one block: lane t adds p[t],
 // p[t + B], p[t + 2B], ... in ascending order (B = blockDim.x), then
 // block_sum.  Loads are issued D at a time, so a lane waits for memory

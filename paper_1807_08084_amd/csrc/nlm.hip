@@ -21,9 +21,10 @@
 #include <algorithm>
 
 #include "../../include/polsar.h"
-#include "pixel.hpp"
+#include "common.hpp"
 
 namespace {
+using polsar_dev::xcd_tile;
 
 constexpr int TW = 64, TH = 4, MAX_R = 16;
 
@@ -57,7 +58,8 @@ __global__ __launch_bounds__(TW * TH) void k_nlm(NlmArgs a) {
   const T* __restrict__ Z = (const T*)a.z;
   const T* __restrict__ A = (const T*)a.aux;
   const int tx = threadIdx.x % TW, ty = threadIdx.x / TW;
-  const int64_t x0 = (int64_t)blockIdx.x * TW, y0 = (int64_t)blockIdx.y * TH;
+  const unsigned t = xcd_tile(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int64_t x0 = (int64_t)(t % gridDim.x) * TW, y0 = (int64_t)(t / gridDim.x) * TH;
   const int64_t px = x0 + tx, py = y0 + ty;
   const bool valid = px < a.W && py < a.H;
   const int r = a.r, bw = TW + 2 * r;

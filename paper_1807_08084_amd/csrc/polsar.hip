@@ -266,7 +266,8 @@ __global__ __launch_bounds__(BOX_TW) void k_boxcar(BoxArgs a) {
   __shared__ double row[2][6][SW];  // staged in FP64 (exact for FP32 input)
   const T* __restrict__ S = (const T*)a.s;
   const int lane = threadIdx.x;
-  const int64_t bx = (int64_t)blockIdx.x % a.nbx, by = (int64_t)blockIdx.x / a.nbx;
+  const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t bx = t % a.nbx, by = t / a.nbx;
   const int64_t x0 = bx * BOX_TW, ys = by * BOX_STRIP;
   const int64_t ye = ys + BOX_STRIP < a.H ? ys + BOX_STRIP : a.H;
   const int64_t y_first = ys - R, y_last = ye - 1 + R;  // rows staged (outside the image: zeros)
