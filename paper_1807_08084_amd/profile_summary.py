@@ -46,14 +46,16 @@ def trace(db: str, out: str, command: str) -> None:
     print(open(out).read())
 
 
-def _counter(db: str, counter: str):
+def _counter(db: str, counter: str, main_grid: bool = False):
+    """Mean value per dispatch, by kernel; with main_grid, over the kernel's
+    dispatches at its most frequent grid size only."""
     con = sqlite3.connect(db)
-    rows = con.execute("select kernel_name, value, workgroup_size from counters_collection where counter_name=?",
+    rows = con.execute("select kernel_name, value, grid_size from counters_collection where counter_name=?",
                        (counter,)).fetchall()
     agg = {}
-    for k, v, w in rows:
-        agg.setdefault(short(k), []).append(v)
-    return {k: statistics.mean(v) for k, v in agg.items()}
+    for k, v, g in rows:
+        agg.setdefault(short(k), {}).setdefault(g if main_grid else 0, []).append(v)
+    return {k: statistics.mean(max(by.values(), key=len)) for k, by in agg.items()}
 
 
 def traffic(fetch_db: str, write_db: str, out: str, command: str, n_px: int = 4096 * 4096) -> None:
@@ -102,9 +104,10 @@ ROW_KERNELS = [
 def traffic_rows(fetch_db: str, write_db: str, out: str, command: str, n_px: int = 4096 * 4096) -> None:
     """HBM bytes per pixel of the bench rows' kernels (FETCH_SIZE / WRITE_SIZE
     per dispatch, scaled by the one-plane copy probe) against their
-    algorithmic bytes."""
-    f = _counter(fetch_db, "FETCH_SIZE")
-    w = _counter(write_db, "WRITE_SIZE")
+    algorithmic bytes.  Each kernel's dispatches at its most frequent grid
+    size are used (the image; the streamer's chunks share kernel names)."""
+    f = _counter(fetch_db, "FETCH_SIZE", main_grid=True)
+    w = _counter(write_db, "WRITE_SIZE", main_grid=True)
 
     def one_plane_copy(k):
         args = k[k.find("<") + 1:k.rfind(">")].split(", ")
