@@ -49,7 +49,7 @@ def _check_z(z_gpu, s_np, H, W, r, u, pixels=None):
     (torch.float32, "adjugate", "compensated"), (torch.float32, "cholesky", "plain"),
     (torch.float64, "adjugate", "compensated"), (torch.float64, "cholesky", "plain")])
 @pytest.mark.parametrize("H,W,r", [(37, 70, 3), (13, 129, 2), (9, 65, 1), (64, 4, 3), (5, 3, 3), (1, 100, 2),
-                                   (20, 20, 0)])
+                                   (20, 20, 0), (70, 300, 2)])  # the last: 15 tiles, more than 8 and not a multiple
 def test_boxcar_equals_two_step(ops, dtype, method, prec, H, W, r):
     s_np = _single_look(H, W, 11 + H)
     if dtype == torch.float32:
