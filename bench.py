@@ -174,7 +174,7 @@ def cpu_baseline(z64: np.ndarray, n_px: int, min_seconds: float = 10.0):
 
 def other_workloads(torch, ops, dev, steps):
     """Each remaining workload timed on its own input (device time, data resident)."""
-    from paper_1807_08084_amd import synth
+    from paper_1807_08084_amd import synth, tune
     from paper_1807_08084_amd.batch import BatchPlan
     res = {}
     # 8192^2 with the 4096^2 recipe (N=4, 4x4 regions, lam in [1e-3, 1]): both forms, FP32 and FP64
@@ -247,7 +247,18 @@ def other_workloads(torch, ops, dev, steps):
         ms = time_calls(lambda: ops.wishart_loglik(st, zt, 8.0, forward=True, backward=True, workspace=ws),
                         steps, 3, torch)
         res[f"wishart_2048_fwd_bwd_{tn}"] = {"gpx_s": round(n / ms / 1e6, 3), "ms": round(ms, 4),
-                                             "GB_s": round(bpp * n / ms / 1e6, 1)}
+                                             "GB_s": round(bpp * n / ms / 1e6, 1),
+                                             "frac_hbm": round(bpp * n / ms / 1e6 / PEAK_HBM_GBS, 4)}
+        # again with the launch the Wishart tuner picks on this image
+        keep = ops.get_launch(1, dt, "adjugate", "plain")
+        cfg, _ = tune.tune_wishart(st, zt, 8.0, reps=10)
+        ms = time_calls(lambda: ops.wishart_loglik(st, zt, 8.0, forward=True, backward=True, workspace=ws),
+                        steps, 3, torch)
+        res[f"wishart_2048_fwd_bwd_{tn}_autotuned"] = {"gpx_s": round(n / ms / 1e6, 3), "ms": round(ms, 4),
+                                                       "GB_s": round(bpp * n / ms / 1e6, 1),
+                                                       "frac_hbm": round(bpp * n / ms / 1e6 / PEAK_HBM_GBS, 4),
+                                                       "launch": cfg}
+        ops.set_launch(1, dt, "adjugate", "plain", keep)
         del zt, st, ws
         torch.cuda.empty_cache()
     print(f"# wishart workload done", file=sys.stderr, flush=True)
