@@ -250,7 +250,8 @@ def other_workloads(torch, ops, dev, steps):
                                              "GB_s": round(bpp * n / ms / 1e6, 1),
                                              "frac_hbm": round(bpp * n / ms / 1e6 / PEAK_HBM_GBS, 4)}
         # again with the launch the Wishart tuner picks on this image
-        keep = ops.get_launch(1, dt, "adjugate", "plain")
+        wop = ops.wishart_launch_op(n)
+        keep = ops.get_launch(wop, dt, "adjugate", "plain")
         cfg, _ = tune.tune_wishart(st, zt, 8.0, reps=10)
         ms = time_calls(lambda: ops.wishart_loglik(st, zt, 8.0, forward=True, backward=True, workspace=ws),
                         steps, 3, torch)
@@ -258,7 +259,7 @@ def other_workloads(torch, ops, dev, steps):
                                                        "GB_s": round(bpp * n / ms / 1e6, 1),
                                                        "frac_hbm": round(bpp * n / ms / 1e6 / PEAK_HBM_GBS, 4),
                                                        "launch": cfg}
-        ops.set_launch(1, dt, "adjugate", "plain", keep)
+        ops.set_launch(wop, dt, "adjugate", "plain", keep)
         del zt, st, ws
         torch.cuda.empty_cache()
     print(f"# wishart workload done", file=sys.stderr, flush=True)

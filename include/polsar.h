@@ -254,10 +254,10 @@ int polsar_streamer_run(polsar_streamer* s, int64_t n, const void* z, int64_t z_
 void polsar_streamer_destroy(polsar_streamer* s);
 
 /* Launch configuration of the kernels, keyed by op (0 = inv_det,
- * 1 = wishart, 2 = multilook + inv_det, 3 = batch, 4 = the copy probe; ops
- * 2, 3 and 4 take unroll 1, op 3 a persistent grid, op 4 one tile per
- * block; ops 1 and 4 are keyed with method 0 and precision 0), dtype,
- * method, precision.
+ * 1 = wishart, 2 = multilook + inv_det, 3 = batch, 4 = the copy probe,
+ * 5 = wishart on images of fewer than 2^23 pixels; ops 2, 3 and 4 take
+ * unroll 1, op 3 a persistent grid, op 4 one tile per block; ops 1, 4 and 5
+ * are keyed with method 0 and precision 0), dtype, method, precision.
  *   block        threads per block: 64, 128 or 256
  *   unroll       vectors per thread per tile: 1, 2 or 4 (the FP32
  *                compensated inverse takes at most 2, sharing one FP64
@@ -273,6 +273,9 @@ void polsar_streamer_destroy(polsar_streamer* s);
 typedef struct { int block, unroll, grid_per_cu, nontemporal, vector_bytes, blocks_per_cu; } polsar_launch;
 int polsar_get_launch(int op, int dtype, int method, int precision, polsar_launch* out);
 int polsar_set_launch(int op, int dtype, int method, int precision, const polsar_launch* cfg);
+/* The op of the table (1 or 5) whose launch polsar_wishart_loglik uses for
+ * n pixels. */
+int polsar_wishart_launch_op(int64_t n);
 
 /* Times each candidate launch configuration of polsar_inv_det on the caller's
  * buffers (same arguments as polsar_inv_det; outputs are overwritten), `reps`

@@ -559,11 +559,19 @@ std::map<std::tuple<int, int, int, int>, polsar_launch> g_cfg;
 // on the 2048x2048 image and stays within 2% of the best on 4096x4096.  The batch kernel (op 3) is a persistent grid.  blocks_per_cu
 // caps the resident blocks: with 4-5 waves per CU the 19 concurrent plane
 // streams of a 3x3 inverse reach ~82% of HBM peak, with more they contend.
+// Images below this many pixels take the Wishart kernel's launch from op 5
+// of the table instead of op 1: on 2048x2048 (2^22 pixels) 8-byte accesses
+// in 128-lane blocks, at most 5 per CU, ran the FP32 fused forward+backward
+// 9-16% faster than the 4096x4096 image's shape, which is 4% faster there.
+constexpr int64_t WISHART_SMALL = int64_t(1) << 23;
+
 polsar_launch default_launch(int op, int dtype, int method, int prec) {
   const bool f64 = dtype == POLSAR_F64, chol = method == POLSAR_CHOLESKY;
   switch (op) {
     case 1:
       return f64 ? polsar_launch{128, 1, 0, 1, 8, 4} : polsar_launch{256, 1, 0, 1, 16, 0};
+    case 5:  // the Wishart kernel below WISHART_SMALL pixels: more, smaller tiles
+      return f64 ? polsar_launch{128, 1, 0, 1, 8, 4} : polsar_launch{128, 1, 0, 1, 8, 5};
     case 2:
       return f64 ? polsar_launch{256, 1, 0, 1, 8, 4} : polsar_launch{128, 1, 0, 1, 16, 0};
     case 3:
@@ -977,14 +985,16 @@ int polsar_device_compute_units(int* cus) {
   return POLSAR_OK;
 }
 
+int polsar_wishart_launch_op(int64_t n) { return n < WISHART_SMALL ? 5 : 1; }
+
 int polsar_get_launch(int op, int dtype, int method, int precision, polsar_launch* out) {
-  if (!out || op < 0 || op > 4) return POLSAR_E_ARG;
+  if (!out || op < 0 || op > 5) return POLSAR_E_ARG;
   *out = get_cfg(op, dtype, method, precision);
   return POLSAR_OK;
 }
 
 int polsar_set_launch(int op, int dtype, int method, int precision, const polsar_launch* cfg) {
-  if (!cfg || op < 0 || op > 4 || !valid_launch(*cfg, op)) return POLSAR_E_ARG;
+  if (!cfg || op < 0 || op > 5 || !valid_launch(*cfg, op)) return POLSAR_E_ARG;
   std::lock_guard<std::mutex> g(g_mu);
   g_cfg[std::make_tuple(op, dtype, method, precision)] = *cfg;
   return POLSAR_OK;
@@ -1160,7 +1170,7 @@ int polsar_wishart_loglik(int dtype, int pass, int64_t n, const void* sigma, int
                 bwd ? grad : nullptr, g_pitch, counters, n, 0, 0, fwd ? 1 : 0, bwd ? 1 : 0};
   const bool vec = vec_ok(sigma, s_pitch, es) && vec_ok(z, z_pitch, es) && (!bwd || vec_ok(grad, g_pitch, es)) &&
                    (!(fwd && ell) || vec_ok(ell, 0, es));
-  const polsar_launch c = get_cfg(1, dtype, 0, 0);
+  const polsar_launch c = get_cfg(polsar_wishart_launch_op(n), dtype, 0, 0);
   hipError_t e = dtype == POLSAR_F32 ? dispatch_wishart<float>(c, vec, a, s) : dispatch_wishart<double>(c, vec, a, s);
   if (e != hipSuccess) return POLSAR_E_HIP;
   if (fwd) {

@@ -324,6 +324,11 @@ def get_launch(op: int, dtype: torch.dtype, method: str = "adjugate", precision:
     return c.as_dict()
 
 
+def wishart_launch_op(n: int) -> int:
+    """The launch-table op (1, or 5 for small images) of a Wishart call on n pixels."""
+    return int(L.lib().polsar_wishart_launch_op(int(n)))
+
+
 def set_launch(op: int, dtype: torch.dtype, method: str, precision: str, cfg: dict) -> None:
     c = L.Launch(**cfg)
     d = L.F32 if dtype == torch.float32 else L.F64

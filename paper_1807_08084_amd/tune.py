@@ -16,7 +16,7 @@ import torch
 
 from . import ops
 
-OPS = {"inv_det": 0, "wishart": 1, "multilook": 2, "batch": 3}
+OPS = {"inv_det": 0, "wishart": 1, "multilook": 2, "batch": 3, "wishart_small": 5}
 
 
 def _time(fn, reps: int) -> float:
@@ -44,16 +44,19 @@ def wishart_candidates():
 
 
 def tune_wishart(sigma: torch.Tensor, z: torch.Tensor, n_looks: float, reps: int = 10):
-    """Sweep the Wishart forward+backward launch; install and return the best."""
-    ws = torch.empty(ops.workspace_bytes(sigma.dtype, sigma[0].numel()) // 8 + 1, dtype=torch.float64,
-                     device=sigma.device)
+    """Sweep the Wishart forward+backward launch; install the best in the
+    table entry that calls of this size use (op 1, or op 5 for small
+    images) and return it."""
+    n = sigma[0].numel()
+    op = ops.wishart_launch_op(n)
+    ws = torch.empty(ops.workspace_bytes(sigma.dtype, n) // 8 + 1, dtype=torch.float64, device=sigma.device)
     best, best_ms = None, float("inf")
     for cfg in wishart_candidates():
-        ops.set_launch(1, sigma.dtype, "adjugate", "plain", cfg)
+        ops.set_launch(op, sigma.dtype, "adjugate", "plain", cfg)
         ms = _time(lambda: ops.wishart_loglik(sigma, z, n_looks, forward=True, backward=True, workspace=ws), reps)
         if ms < best_ms:
             best, best_ms = cfg, ms
-    ops.set_launch(1, sigma.dtype, "adjugate", "plain", best)
+    ops.set_launch(op, sigma.dtype, "adjugate", "plain", best)
     return best, best_ms
 
 

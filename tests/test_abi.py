@@ -113,11 +113,16 @@ def test_launch_table(lib):
     got = L.Launch()
     lib.polsar_get_launch(0, L.F64, L.CHOLESKY, L.PLAIN, ctypes.byref(got))
     assert got.as_dict() == good.as_dict()
-    # op 4, the copy probe: one tile per block, unroll 1; op 5 does not exist
+    # op 4, the copy probe: one tile per block, unroll 1
     assert lib.polsar_get_launch(4, L.F32, 0, 0, ctypes.byref(got)) == L.OK
     assert got.unroll == 1 and got.grid_per_cu == 0
     assert lib.polsar_set_launch(4, L.F32, 0, 0, ctypes.byref(good)) == L.E_ARG
-    assert lib.polsar_get_launch(5, L.F32, 0, 0, ctypes.byref(got)) == L.E_ARG
+    # op 5, the Wishart kernel on small images, and the op a call of n pixels uses;
+    # op 6 does not exist
+    assert lib.polsar_get_launch(5, L.F32, 0, 0, ctypes.byref(got)) == L.OK
+    assert lib.polsar_get_launch(6, L.F32, 0, 0, ctypes.byref(got)) == L.E_ARG
+    assert lib.polsar_wishart_launch_op(2048 * 2048) == 5 and lib.polsar_wishart_launch_op(4096 * 4096) == 1
+    assert lib.polsar_wishart_launch_op((1 << 23) - 1) == 5 and lib.polsar_wishart_launch_op(1 << 23) == 1
 
 
 def test_batch_and_copy_argument_errors(lib):

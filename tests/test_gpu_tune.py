@@ -46,19 +46,21 @@ def test_tune_wishart_and_json_round_trip(ops, tmp_path):
     img = synth.workload_small()
     z = torch.from_numpy(img.planes.reshape(9, -1)).to("cuda", torch.float32)
     s = torch.from_numpy(synth.wishart_sigma0(img.planes.reshape(9, -1))).to("cuda", torch.float32)
-    keep = ops.get_launch(1, torch.float32, "adjugate", "plain")
+    op = ops.wishart_launch_op(z.shape[1])
+    assert op == 5  # a 256x256 image is a small one
+    keep = ops.get_launch(op, torch.float32, "adjugate", "plain")
     loss0, grad0, _ = ops.wishart_loglik(s, z, 4.0, forward=True, backward=True)
     try:
         cfg, ms = tune.tune_wishart(s, z, 4.0, reps=2)
-        assert ms > 0 and ops.get_launch(1, torch.float32, "adjugate", "plain") == cfg
+        assert ms > 0 and ops.get_launch(op, torch.float32, "adjugate", "plain") == cfg
         loss, grad, _ = ops.wishart_loglik(s, z, 4.0, forward=True, backward=True)
         torch.cuda.synchronize()
         assert torch.equal(grad, grad0)
         assert abs(loss.item() - loss0.item()) <= 1e-12 * abs(loss0.item())
         path = str(tmp_path / "launch.json")
-        tune.save(path, {"wishart/f32/adjugate/plain": {"cfg": cfg, "ms": ms}})
-        ops.set_launch(1, torch.float32, "adjugate", "plain", keep)
+        tune.save(path, {"wishart_small/f32/adjugate/plain": {"cfg": cfg, "ms": ms}})
+        ops.set_launch(op, torch.float32, "adjugate", "plain", keep)
         assert tune.load(path) == 1
-        assert ops.get_launch(1, torch.float32, "adjugate", "plain") == cfg
+        assert ops.get_launch(op, torch.float32, "adjugate", "plain") == cfg
     finally:
-        ops.set_launch(1, torch.float32, "adjugate", "plain", keep)
+        ops.set_launch(op, torch.float32, "adjugate", "plain", keep)

@@ -147,15 +147,16 @@ def test_every_launch_shape_with_minimal_workspace(ops, case, dtype, n_cut):
     nbytes = ops.workspace_bytes(dtype, n)
     assert nbytes == max(1, (n + 63) // 64) * 8
     ref = math.fsum(r["eh"][:n]) + math.fsum(r["el"][:n])
-    keep = ops.get_launch(1, dtype, "adjugate", "plain")
+    op = ops.wishart_launch_op(n)
+    keep = ops.get_launch(op, dtype, "adjugate", "plain")
     grads = []
     try:
         for block in (64, 128, 256):
             for unroll in (1, 2):
                 for vb, gpc in ((16, 0), (8, 8)):
-                    ops.set_launch(1, dtype, "adjugate", "plain", dict(block=block, unroll=unroll, grid_per_cu=gpc,
-                                                                       nontemporal=1, vector_bytes=vb,
-                                                                       blocks_per_cu=0))
+                    ops.set_launch(op, dtype, "adjugate", "plain", dict(block=block, unroll=unroll, grid_per_cu=gpc,
+                                                                        nontemporal=1, vector_bytes=vb,
+                                                                        blocks_per_cu=0))
                     ws = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
                     loss, g, _ = ops.wishart_loglik(S, Z, N, forward=True, backward=True, workspace=ws)
                     torch.cuda.synchronize()
@@ -163,5 +164,5 @@ def test_every_launch_shape_with_minimal_workspace(ops, case, dtype, n_cut):
                     assert abs(loss.item() - ref) <= tol * abs(ref), (block, unroll, vb, gpc)
                     grads.append(g)
     finally:
-        ops.set_launch(1, dtype, "adjugate", "plain", keep)
+        ops.set_launch(op, dtype, "adjugate", "plain", keep)
     assert all(torch.equal(grads[0], g) for g in grads[1:])
