@@ -24,10 +24,11 @@ def ops():
     return o
 
 
-def same_loss(ops, dtype, a, b):
-    """Bitwise when the batch cuts tiles like the per-call Wishart kernel,
-    else equal to rounding of the FP64 sums."""
-    w, bt = ops.get_launch(1, dtype, "adjugate", "plain"), ops.get_launch(3, dtype, "adjugate", "compensated")
+def same_loss(ops, dtype, a, b, n):
+    """Bitwise when the batch cuts tiles like the per-call Wishart kernel on
+    an image of n pixels, else equal to rounding of the FP64 sums."""
+    w = ops.get_launch(ops.wishart_launch_op(n), dtype, "adjugate", "plain")
+    bt = ops.get_launch(3, dtype, "adjugate", "compensated")
     if (w["block"], w["vector_bytes"], w["unroll"]) == (bt["block"], bt["vector_bytes"], 1):
         return a == b
     return abs(a - b) <= 1e-12 * abs(b)
@@ -63,7 +64,7 @@ def test_batch_graph_equals_per_image_calls(ops, dtype):
         torch.cuda.synchronize()
         assert torch.equal(plan.inv[i], inv) and torch.equal(plan.det[i], det) and torch.equal(plan.status[i], st)
         assert torch.equal(plan.grad[i], grad) and torch.equal(plan.ell[i], ell)
-        assert same_loss(ops, dtype, plan.loss[i].item(), loss.item())
+        assert same_loss(ops, dtype, plan.loss[i].item(), loss.item(), im["z"][0].numel())
     assert torch.equal(ctr, ctr_loop)
     plan.close()
 
