@@ -16,7 +16,8 @@
  * of one call.  pitch >= n.  Pointers must be aligned to the element size;
  * when every plane base is 16-byte aligned (base and pitch*element size
  * multiples of 16, and the status plane 4-byte aligned for F32, 2-byte for
- * F64) the kernels move 128 bits per access, otherwise one element.
+ * F64) the kernels move 64 or 128 bits per access (the launch table's
+ * vector_bytes), otherwise one element.
  *
  * MEMORY AND STREAMS.  Unless stated, pointers are DEVICE pointers on the
  * current HIP device; the caller allocates and owns every buffer, the library
