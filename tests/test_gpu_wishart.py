@@ -166,3 +166,29 @@ def test_every_launch_shape_with_minimal_workspace(ops, case, dtype, n_cut):
     finally:
         ops.set_launch(op, dtype, "adjugate", "plain", keep)
     assert all(torch.equal(grads[0], g) for g in grads[1:])
+
+
+@pytest.mark.parametrize("width", [4095, 4097])
+def test_both_launch_entries_at_the_size_boundary(ops, width):
+    """2048 x 4095 and 2048 x 4097 pixels sit on either side of 2^23, where
+    the Wishart call switches launch entry (op 5 below, op 1 from there on):
+    the loss against the FP64 oracle's, and the gradient on sampled pixels
+    against the oracle's."""
+    n = 2048 * width
+    assert ops.wishart_launch_op(n) == (5 if n < (1 << 23) else 1)
+    img = synth.make_image(2048, width, 8, (2, 2), (1e-2, 1.0), 17)
+    z = img.planes.reshape(9, -1).astype(np.float32).astype(np.float64)
+    s = synth.wishart_sigma0(z).astype(np.float32).astype(np.float64)
+    Z = torch.from_numpy(z).to("cuda", torch.float32)
+    S = torch.from_numpy(s).to("cuda", torch.float32)
+    loss, g, _ = ops.wishart_loglik(S, Z, N, forward=True, backward=True)
+    torch.cuda.synchronize()
+    ell, _ = oracle.wishart(s, z, N, grad=False)
+    ref = math.fsum(ell)
+    assert abs(loss.item() - ref) <= 1e-5 * abs(ref)
+    idx = np.sort(np.random.default_rng(width).choice(n, 4000, replace=False))
+    (_, _), (gh, gl) = oracle.wishart128(s[:, idx], z[:, idx], N)
+    ks = oracle.kappa(s[:, idx])
+    d = (to_np(g).reshape(9, -1)[:, idx] - gh) - gl
+    err = np.linalg.norm(d, axis=0) / np.linalg.norm(gh, axis=0)
+    assert np.all(err <= 2e-6 * ks * ks), err.max()
