@@ -97,7 +97,7 @@ ROW_KERNELS = [
     ("k_wishart<float, 4, 1, true>", "FP32 Wishart fwd+bwd", 72, 36),
     ("k_wishart<double, 1, 1, true>", "FP64 Wishart fwd+bwd", 144, 72),
     ("k_boxcar<float, 1, 1>", "boxcar 3x3 (halo rows: +2/32 of the reads)", 24, 40),
-    ("k_boxcar<float, 1, 3>", "boxcar 7x7 (halo rows: +6/32 of the reads)", 24, 40),
+    ("k_boxcar<float, 1, 3>", "boxcar 7x7 (halo rows: +6/64 of the reads)", 24, 40),
 ]
 
 
