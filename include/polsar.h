@@ -189,7 +189,10 @@ typedef enum { POLSAR_FWD = 1, POLSAR_BWD = 2, POLSAR_FWD_BWD = 3 } polsar_pass;
  *   workspace  device scratch of at least polsar_wishart_workspace_bytes(n)
  *              bytes (FWD, FWD_BWD), 8-byte aligned; holds per-tile FP64
  *              partial sums, reduced in a fixed order (deterministic).
- *   counters   as for polsar_inv_det ([not_pd, 0, nonfinite] for S). */
+ *   counters   as for polsar_inv_det ([not_pd, 0, nonfinite] for S).
+ * Launch shape: op 1 of polsar_get_launch, op 5 below 2^23 pixels (see
+ * polsar_wishart_launch_op); the loss's summation order follows the tiles,
+ * so it can differ between the two in the last bits. */
 int polsar_wishart_loglik(int dtype, int pass, int64_t n,
                           const void* sigma, int64_t s_pitch,
                           const void* z, int64_t z_pitch, double n_looks,
