@@ -202,15 +202,21 @@ int polsar_wishart_loglik(int dtype, int pass, int64_t n,
                           unsigned long long* counters, void* stream);
 size_t polsar_wishart_workspace_bytes(int dtype, int64_t n);
 
-/* Batched persistent launch over many images of uneven sizes (one grid walks
- * the tiles of all images; the launch and the per-image loss reduction are
- * captured once in a HIP graph).  Per image, any of: inverse/determinant of
- * Z (ops & POLSAR_OP_INV_DET), Wishart forward (loss, ell) and backward
- * (grad) of S against Z (ops & POLSAR_OP_WISHART_FWD / _BWD).  Host array
+/* Batched persistent launch over many images of uneven sizes: the paper's
+ * closing section names, as future work, combining several matrix
+ * inversions into a single inversion call; here one call (one graph launch)
+ * covers every pixel of every image.  One grid walks the tiles of all
+ * images; the launch and the per-image loss reduction are captured once in
+ * a HIP graph.  Per image, any of: inverse/determinant of Z (ops &
+ * POLSAR_OP_INV_DET, Alg. 2 or Alg. 1 as for polsar_inv_det), Wishart
+ * forward (loss, ell) and backward (grad) of S against Z (ops &
+ * POLSAR_OP_WISHART_FWD / _BWD, as for polsar_wishart_loglik).  Host array
  * `imgs`; the pointers inside are device pointers with the meaning above,
  * `loss` one device double per image.  grad_loss (device double, nullable =
- * 1.0) scales every gradient.  Each image's outputs must not overlap its
- * inputs or each other (POLSAR_E_ALIAS); in-place is not offered here. */
+ * 1.0) scales every gradient.  Every image runs in the same grid, so no
+ * output of any image (inv, det, status, grad, ell, loss) may overlap an
+ * input or another output of any image (POLSAR_E_ALIAS); inputs may be
+ * shared between images; in-place is not offered here. */
 enum { POLSAR_OP_INV_DET = 1, POLSAR_OP_WISHART_FWD = 2, POLSAR_OP_WISHART_BWD = 4 };
 typedef struct {
   int64_t n;
@@ -226,8 +232,8 @@ typedef struct {
 } polsar_image;
 typedef struct polsar_batch polsar_batch;
 
-/* Allocates device tables, a workspace and the graph (the only call that
- * allocates).  method: POLSAR_ADJUGATE or POLSAR_CHOLESKY for the inverse;
+/* Create: allocates device tables, a workspace and the graph (the only call
+ * that allocates).  method: POLSAR_ADJUGATE or POLSAR_CHOLESKY for the inverse;
  * the launch shape is the op-3 entry of the launch table, grid_per_cu > 0
  * overrides its blocks per compute unit.  Returns POLSAR_OK and *out, or an error
  * (no allocation left behind). */

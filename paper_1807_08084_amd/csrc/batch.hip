@@ -301,6 +301,28 @@ void release(polsar_batch* b) {
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+// Byte range [lo, hi) of some planes of one image.
+struct Span {
+  uintptr_t lo, hi;
+  bool out;
+};
+
+// True when no output span overlaps another span (input or output).  Sorted
+// by start, a span overlaps an earlier one of some kind exactly when it
+// starts before the furthest end among the earlier spans of that kind.
+bool disjoint_outputs(std::vector<Span>& v) {
+  std::sort(v.begin(), v.end(), [](const Span& a, const Span& b) { return a.lo < b.lo; });
+  uintptr_t end_in = 0, end_out = 0;
+  for (const Span& x : v) {
+    if (x.hi <= x.lo) continue;
+    if (x.lo < end_out) return false;            // meets an earlier output
+    if (x.out && x.lo < end_in) return false;    // an output meets an earlier input
+    if (x.out) end_out = std::max(end_out, x.hi);
+    else end_in = std::max(end_in, x.hi);
+  }
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -330,6 +352,8 @@ int polsar_batch_create(const polsar_image* imgs, int count, int dtype, int meth
   const bool half = use.vector_bytes == 8;
   const int VW = (int)((half ? 8 : 16) / es);
   std::vector<ImgDesc> h(count);
+  std::vector<Span> spans;
+  spans.reserve((size_t)count * 7);
   int64_t tiles = 0;
   for (int i = 0; i < count; ++i) {
     const polsar_image& m = imgs[i];
@@ -359,28 +383,25 @@ int polsar_batch_create(const polsar_image* imgs, int count, int dtype, int meth
       if (!planes_ok(m.grad, m.g_pitch)) return POLSAR_E_ARG;
       vec = vec && aligned(m.grad, 16) && (m.g_pitch * (int64_t)es) % 16 == 0;
     }
-    {  // this image's outputs must not overlap its inputs or each other
-      auto rng = [&](const void* p, int planes, int64_t pitch, size_t e) {
+    {  // this image's byte ranges, checked against every image's below
+      auto add = [&](const void* p, int planes, int64_t pitch, size_t e, bool is_out) {
+        if (!p) return;
         const uintptr_t lo = (uintptr_t)p;
-        return std::make_pair(lo, p ? lo + (uintptr_t)(((planes - 1) * pitch + m.n) * (int64_t)e) : lo);
+        spans.push_back(Span{lo, lo + (uintptr_t)(((planes - 1) * pitch + m.n) * (int64_t)e), is_out});
       };
       const bool wish = ops & (POLSAR_OP_WISHART_FWD | POLSAR_OP_WISHART_BWD);
       const bool inv_op = ops & POLSAR_OP_INV_DET;
-      const std::pair<uintptr_t, uintptr_t> in[2] = {rng(m.z, 9, m.z_pitch, es),
-                                                     rng(wish ? m.sigma : nullptr, 9, m.s_pitch, es)};
-      const std::pair<uintptr_t, uintptr_t> out[5] = {
-          rng(inv_op ? m.inv : nullptr, 9, m.inv_pitch, es), rng(inv_op ? m.det : nullptr, 1, m.n, es),
-          rng(inv_op ? (const void*)m.status : nullptr, 1, m.n, 1),
-          rng((ops & POLSAR_OP_WISHART_BWD) ? m.grad : nullptr, 9, m.g_pitch, es),
-          rng((ops & POLSAR_OP_WISHART_FWD) ? m.ell : nullptr, 1, m.n, es)};
-      auto ov = [](std::pair<uintptr_t, uintptr_t> x, std::pair<uintptr_t, uintptr_t> y) {
-        return x.second > x.first && y.second > y.first && x.first < y.second && y.first < x.second;
-      };
-      for (int p = 0; p < 5; ++p) {
-        for (int q = 0; q < 2; ++q)
-          if (ov(out[p], in[q])) return POLSAR_E_ALIAS;
-        for (int q = p + 1; q < 5; ++q)
-          if (ov(out[p], out[q])) return POLSAR_E_ALIAS;
+      add(m.z, 9, m.z_pitch, es, false);
+      if (wish) add(m.sigma, 9, m.s_pitch, es, false);
+      if (inv_op) {
+        add(m.inv, 9, m.inv_pitch, es, true);
+        add(m.det, 1, m.n, es, true);
+        add(m.status, 1, m.n, 1, true);
+      }
+      if (ops & POLSAR_OP_WISHART_BWD) add(m.grad, 9, m.g_pitch, es, true);
+      if (ops & POLSAR_OP_WISHART_FWD) {
+        add(m.ell, 1, m.n, es, true);
+        if (m.loss) spans.push_back(Span{(uintptr_t)m.loss, (uintptr_t)m.loss + sizeof(double), true});
       }
     }
     ImgDesc& d = h[i];
@@ -405,6 +426,9 @@ int polsar_batch_create(const polsar_image* imgs, int count, int dtype, int meth
     d.tile0 = tiles;
     tiles += d.ntiles;
   }
+  // One grid runs every image at once, so no output may overlap any input or
+  // any other output of any image (inputs may be shared).
+  if (!disjoint_outputs(spans)) return POLSAR_E_ALIAS;
   polsar_batch* b = new polsar_batch();
   b->dtype = dtype;
   b->count = count;

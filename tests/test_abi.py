@@ -140,6 +140,18 @@ def test_batch_and_copy_argument_errors(lib):
     assert lib.polsar_batch_create(ok, 1, L.F32, L.ADJUGATE, L.COMPENSATED, 1, None, None, 0, ctypes.byref(h)) == L.E_ALIAS
     ok[0].inv, ok[0].det = FAKE2, FAKE2 + 1024                        # det inside the inverse planes
     assert lib.polsar_batch_create(ok, 1, L.F32, L.ADJUGATE, L.COMPENSATED, 1, None, None, 0, ctypes.byref(h)) == L.E_ALIAS
+    # one grid runs all images at once: an output of one image may not overlap
+    # another image's input or output (inputs may be shared)
+    two = (L.Image * 2)()
+    for i in range(2):
+        two[i].n, two[i].z, two[i].z_pitch = 64, FAKE, 64                   # both read the same z
+        two[i].inv, two[i].inv_pitch, two[i].det = FAKE2 + 4096 * i, 64, FAKE3 + 1024 * i
+    two[1].inv = FAKE2 + 256                                              # image 1's inverse inside image 0's
+    assert lib.polsar_batch_create(two, 2, L.F32, L.ADJUGATE, L.COMPENSATED, 1, None, None, 0, ctypes.byref(h)) == L.E_ALIAS
+    two[1].inv, two[1].det = FAKE2 + 4096, FAKE + 128                      # image 1's det inside image 0's z
+    assert lib.polsar_batch_create(two, 2, L.F32, L.ADJUGATE, L.COMPENSATED, 1, None, None, 0, ctypes.byref(h)) == L.E_ALIAS
+    two[1].det = FAKE3                                                     # the two det planes coincide
+    assert lib.polsar_batch_create(two, 2, L.F32, L.ADJUGATE, L.COMPENSATED, 1, None, None, 0, ctypes.byref(h)) == L.E_ALIAS
     assert lib.polsar_batch_run(None, None) == L.E_ARG
     assert lib.polsar_batch_tiles(None) == -1
     assert lib.polsar_stream_copy(L.F32, 100, FAKE, 100, 5, FAKE2, 100, 10, None) == L.E_UNSUPPORTED

@@ -400,3 +400,123 @@ def test_boxcar_oracle():
         y, x = divmod(p, W)
         want = ov / counts[p] if (abs(y - y0) <= r and abs(x - x0) <= r) else np.zeros(9)
         assert np.array_equal(z[:, p], want)
+
+
+# --------------------------------------------------------------- error metrics and kappa
+# Every kappa-scaled tolerance and every error figure of the parity tests
+# goes through these three functions, so each is pinned to a closed form or
+# to an independent computation (full complex matrices, numpy's Frobenius
+# norm, exact rationals), chosen so that a wrong weight, a dropped low word,
+# a wrong denominator or an inflated kappa fails.
+
+def test_kappa_closed_forms():
+    z = np.zeros((9, 6))
+    z[0:3, 0] = 1.0                                  # identity
+    z[0:3, 1] = (4.0, 0.5, 2.0)                      # diagonal: 4 / 0.5
+    z[0:3, 2] = (1.0, 1.0, 0.0)                      # singular (exact zero eigenvalue)
+    z[0:3, 3] = (1.0, -2.0, 3.0)                     # indefinite
+    # 2x2 block [[a, b], [conj b, d]] with f: eigenvalues (a+d)/2 +- sqrt(((a-d)/2)^2 + |b|^2), f
+    z[0, 4], z[1, 4], z[2, 4], z[3, 4], z[4, 4] = 5.0, 2.0, 1.5, 1.2, -1.6   # |b| = 2, disc = sqrt(2.25 + 4) = 2.5
+    z[0:3, 5] = (1.0, 1.0, 1.0)
+    z[7, 5], z[8, 5] = 0.6, 0.8                      # |e| = 1 on a unit diagonal: eigenvalues 2, 1, 0 -> singular
+    k = oracle.kappa(z)
+    assert k[0] == 1.0
+    assert k[1] == 8.0
+    assert np.isinf(k[2]) and np.isinf(k[3])
+    assert abs(k[4] - 6.0) <= 8 * U64 * 6.0, k[4]
+    assert k[5] > 1e15 or np.isinf(k[5])            # rounding may leave a tiny positive eigenvalue
+
+
+def test_kappa_of_matrices_with_known_spectrum():
+    """kappa of H diag(lam) H^H against lam_max / lam_min.  H = I - v v^H / 2
+    with v = (1, 1+i, 1) (|v|^2 = 4) is exactly unitary in binary floating
+    point, and so are its products with exact phase and permutation
+    matrices, so the stored matrix has the spectrum lam up to the rounding
+    of its entries (about u64 lam_max): kappa is then known to a few
+    u64 * kappa.  Haar-rotated matrices (Gram-Schmidt, unitary to rounding)
+    are checked to 1e-12 kappa."""
+    rng = np.random.default_rng(41)
+    v = np.array([1.0, 1.0 + 1.0j, 1.0])
+    H = np.eye(3) - np.outer(v, v.conj()) / 2.0
+    phases = [np.diag(d) for d in ((1, 1j, -1), (1j, 1, -1j), (-1, -1j, 1))]
+    perms = [np.eye(3)[list(p)] for p in itertools.permutations(range(3))]
+    for klog in (0.0, 1.0, 3.0, 6.0, 8.0, 10.0):
+        m = 400
+        mid = rng.uniform(0.0, 1.0, size=m)
+        small = rng.uniform(0.0, 1.0, size=m) < 0.5  # one or two small eigenvalues
+        lam2 = np.where(small, 10.0 ** (-klog * mid), 10.0 ** (-klog * mid * 0.1))
+        eig = np.stack([np.ones(m), lam2, np.full(m, 10.0 ** -klog)], axis=1)
+        kt = eig.max(1) / eig.min(1)
+        Q = [phases[i % 3] @ H @ perms[i % 6] for i in range(m)]
+        Z = np.stack([q @ np.diag(e) @ q.conj().T for q, e in zip(Q, eig)])
+        rel = np.abs(oracle.kappa(synth.pack(Z)) - kt) / kt
+        assert np.all(rel <= 16 * U64 * kt), (klog, (rel / (U64 * kt)).max())
+        rel = np.abs(oracle.kappa(hpd(rng, m, eig)) - kt) / kt
+        assert np.all(rel <= 1e-12 * kt), (klog, rel.max())
+    # the pinned formula fails for the plausible mistakes
+    z = hpd(rng, 8, np.array([[1.0, 0.1, 1e-4]] * 8))
+    w = np.linalg.eigvalsh(oracle.full_from_planes(z))
+    assert not np.allclose(oracle.kappa(z), np.sqrt(w[:, -1] / w[:, 0]))  # not the square root
+    assert not np.allclose(oracle.kappa(z), w[:, -1] / w[:, 1])           # not the middle eigenvalue
+
+
+def _frob_full(p):
+    """Frobenius norms of the full Hermitian matrices of (9, n) planes (numpy's own norm)."""
+    return np.linalg.norm(oracle.full_from_planes(p), axis=(1, 2))
+
+
+def test_inv_rel_err_closed_forms():
+    rng = np.random.default_rng(42)
+    ref = hpd(rng, 16, np.array([[1.0, 0.5, 0.25]] * 16))
+    nrm = _frob_full(ref)
+    eps = 2.0 ** -30
+    for plane in range(9):
+        x = ref.copy()
+        x[plane] += eps
+        want = (eps if plane < 3 else math.sqrt(2.0) * eps) / nrm   # an off-diagonal entry appears twice
+        got = oracle.inv_rel_err(x, ref)
+        assert np.allclose(got, want, rtol=1e-6, atol=0), (plane, got[:2], want[:2])
+    # a general perturbation against the full-matrix definition
+    x = ref + 1e-7 * rng.standard_normal(ref.shape)
+    want = _frob_full(x - ref) / nrm
+    assert np.allclose(oracle.inv_rel_err(x, ref), want, rtol=1e-9)
+    # identical input has zero error
+    assert np.all(oracle.inv_rel_err(ref, ref) == 0.0)
+
+
+def test_inv_rel_err_with_low_word_exact():
+    """Reference given as hi + lo: the error is measured from hi + lo, exactly
+    as a rational computation says (up to the final rounding)."""
+    rng = np.random.default_rng(43)
+    m = 64
+    hi = rng.uniform(-1, 1, (9, m))
+    hi[0:3] = np.abs(hi[0:3]) + 1.0
+    lo = hi * rng.uniform(-1, 1, (9, m)) * 2.0 ** -54   # below half an ulp of hi
+    x = hi.copy()
+    x[:, m // 2:] += hi[:, m // 2:] * rng.uniform(-1, 1, (9, m - m // 2)) * 2.0 ** -52  # within an ulp or two
+    got = oracle.inv_rel_err(x, hi, lo)
+    w = [1, 1, 1, 2, 2, 2, 2, 2, 2]
+    for j in range(m):
+        num = sum(w[k] * (F(x[k, j]) - F(hi[k, j]) - F(lo[k, j])) ** 2 for k in range(9))
+        den = sum(w[k] * F(hi[k, j]) ** 2 for k in range(9))
+        want = math.sqrt(float(num / den))
+        assert abs(got[j] - want) <= 1e-6 * want, (j, got[j], want)
+    # the low word matters at this scale: without it an exact hi has no error
+    assert np.all(oracle.inv_rel_err(x[:, :m // 2], hi[:, :m // 2]) == 0.0)
+    assert np.all(got[:m // 2] > 0.0)
+
+
+def test_det_rel_err_closed_forms_and_low_word():
+    ref = np.array([1.0, -4.0, 2.0 ** -40, 3.0])
+    d = ref * (1.0 + 2.0 ** -20)
+    assert np.array_equal(oracle.det_rel_err(d, ref), np.full(4, 2.0 ** -20))
+    assert np.array_equal(oracle.det_rel_err(-ref, ref), np.full(4, 2.0))  # sign errors count
+    # hi + lo reference, exact rationals
+    hi = np.array([1.0, -3.0, 0.7, 1e-10])
+    lo = np.array([2.0 ** -60, 2.0 ** -57, -1e-17 * 0.7 / 2, 3e-27])
+    dd = hi + np.array([0.0, 2.0 ** -51, 2.0 ** -52, 0.0])
+    got = oracle.det_rel_err(dd, hi, lo)
+    for j in range(4):
+        want = abs(F(dd[j]) - F(hi[j]) - F(lo[j])) / abs(F(hi[j]))
+        assert abs(got[j] - float(want)) <= 1e-12 * float(want), (j, got[j], float(want))
+    assert got[0] == 2.0 ** -60  # an exact result still has the low word's error
