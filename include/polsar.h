@@ -265,9 +265,10 @@ void polsar_streamer_destroy(polsar_streamer* s);
 
 /* Launch configuration of the kernels, keyed by op (0 = inv_det,
  * 1 = wishart, 2 = multilook + inv_det, 3 = batch, 4 = the copy probe,
- * 5 = wishart on images of fewer than 2^23 pixels; ops 2, 3 and 4 take
- * unroll 1, op 3 a persistent grid, op 4 one tile per block; ops 1, 4 and 5
- * are keyed with method 0 and precision 0), dtype, method, precision.
+ * 5 = wishart on images of fewer than 2^23 pixels, 6 = inv_det on images of
+ * at least 2^25 pixels; ops 2, 3 and 4 take unroll 1, op 3 a persistent
+ * grid, op 4 one tile per block; ops 1, 4 and 5 are keyed with method 0 and
+ * precision 0), dtype, method, precision.
  *   block        threads per block: 64, 128 or 256
  *   unroll       vectors per thread per tile: 1, 2 or 4 (the FP32
  *                compensated inverse takes at most 2, sharing one FP64
@@ -286,12 +287,16 @@ int polsar_set_launch(int op, int dtype, int method, int precision, const polsar
 /* The op of the table (1 or 5) whose launch polsar_wishart_loglik uses for
  * n pixels. */
 int polsar_wishart_launch_op(int64_t n);
+/* The op of the table (0 or 6) whose launch polsar_inv_det (and each chunk of
+ * the streamer) uses for n pixels. */
+int polsar_inv_det_launch_op(int64_t n);
 
 /* Times each candidate launch configuration of polsar_inv_det on the caller's
  * buffers (same arguments as polsar_inv_det; outputs are overwritten), `reps`
  * timed repetitions each after one warm-up; the six fastest are timed again
  * in three interleaved passes and ranked by their best pass.  Installs the
- * winner and returns it with that mean time per call in milliseconds.
+ * winner in the entry that calls of n pixels use (polsar_inv_det_launch_op)
+ * and returns it with that mean time per call in milliseconds.
  * Synchronises `stream`. */
 int polsar_autotune_inv_det(int dtype, int method, int precision, int64_t n,
                             const void* z, int64_t z_pitch, void* inv, int64_t inv_pitch,

@@ -80,6 +80,7 @@ def lib():
         L.polsar_get_launch.argtypes = [i, i, i, i, ctypes.POINTER(Launch)]
         L.polsar_set_launch.argtypes = [i, i, i, i, ctypes.POINTER(Launch)]
         L.polsar_wishart_launch_op.argtypes = [i64]
+        L.polsar_inv_det_launch_op.argtypes = [i64]
         L.polsar_autotune_inv_det.argtypes = [i, i, i, i64, vp, i64, vp, i64, vp, i, ctypes.POINTER(Launch),
                                               ctypes.POINTER(ctypes.c_float), vp]
         L.polsar_stream_copy.argtypes = [i, i64, vp, i64, i, vp, i64, i, vp]

@@ -145,7 +145,10 @@ __device__ __forceinline__ int run_pixel(const T (&z)[9], T (&x)[9], T& det) {
 // would free the owners earlier; measured, those scattered 4-byte stores
 // made the kernel slower than the LDS round trip.)
 // Queue: 64*U*V entries of QUEUE_WORDS floats (9 inputs, then 9 outputs +
-// det), then 64*U*V status bytes.  valid[u] is false for vectors past the
+// det), stored word-major (word k of entry e at q[k*64*U*V + e], so that
+// each word of a pixel is one LDS access at an immediate offset from the
+// same address and consecutive entries fall in consecutive banks), then
+// 64*U*V status bytes.  valid[u] is false for vectors past the
 // end of the image; those take no step and are not queued.  load(u, in)
 // fills the 9 planes of vector u.  Every lane of the wave that is active at
 // the call takes part (ballots); inactive lanes neither queue nor drain.
@@ -154,6 +157,7 @@ constexpr int QUEUE_WORDS = 10;
 template <int U, int V, class Load>
 __device__ __forceinline__ void comp_f32_wave(const Load& load, const bool (&valid)[U], float (&out)[U][9][V],
                                               float (&dt)[U][V], int (&st)[U][V], float* q, uint8_t* qs) {
+  constexpr int E = 64 * U * V;  // entries: the stride between a pixel's words
   const int lane = threadIdx.x & 63;
   const unsigned long long below = lane == 0 ? 0ull : ((1ull << lane) - 1ull);
   unsigned long long mask[U][V];
@@ -181,7 +185,7 @@ __device__ __forceinline__ void comp_f32_wave(const Load& load, const bool (&val
       if (need) {
         const int pos = total + __popcll(mask[u][l] & below);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) q[pos * QUEUE_WORDS + k] = in[k][l];
+        for (int k = 0; k < 9; ++k) q[k * E + pos] = in[k][l];
       }
       total += __popcll(mask[u][l]);
     }
@@ -196,11 +200,11 @@ __device__ __forceinline__ void comp_f32_wave(const Load& load, const bool (&val
   for (int e = rank; e < total; e += nact) {
     float zz[9], xx[9], d;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) zz[k] = q[e * QUEUE_WORDS + k];
+    for (int k = 0; k < 9; ++k) zz[k] = q[k * E + e];
     const int sst = px::adjugate_comp_reroute(zz, xx, d);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) q[e * QUEUE_WORDS + k] = xx[k];
-    q[e * QUEUE_WORDS + 9] = d;
+    for (int k = 0; k < 9; ++k) q[k * E + e] = xx[k];
+    q[9 * E + e] = d;
     qs[e] = (uint8_t)sst;
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -214,8 +218,8 @@ __device__ __forceinline__ void comp_f32_wave(const Load& load, const bool (&val
       if ((mask[u][l] >> lane) & 1ull) {
         const int pos = base + __popcll(mask[u][l] & below);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) out[u][k][l] = q[pos * QUEUE_WORDS + k];
-        dt[u][l] = q[pos * QUEUE_WORDS + 9];
+        for (int k = 0; k < 9; ++k) out[u][k][l] = q[k * E + pos];
+        dt[u][l] = q[9 * E + pos];
         st[u][l] = qs[pos];
       }
       base += __popcll(mask[u][l]);

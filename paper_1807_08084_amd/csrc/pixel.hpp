@@ -262,7 +262,9 @@ constexpr float REROUTE_REL = 1e-6f;
 // inputs and rounded to FP32 (status ST_REROUTED when that succeeds).
 //
 // adjugate_comp_try: the FP32 step; returns true and the result when the
-// pixel is accepted, false when it must be recomputed.
+// pixel is accepted, false when it must be recomputed (x then holds the
+// scaled FP32 cofactors, which the recompute replaces: scaling every pixel
+// costs less than branching around the scale).
 PX_HD bool adjugate_comp_try(const float z[9], float x[9], float& det, float* bound_out = nullptr) {
   DW<float> c[9];
   float rerr[9], bound;
@@ -272,7 +274,7 @@ PX_HD bool adjugate_comp_try(const float z[9], float x[9], float& det, float* bo
   const float t = 1.0f / det;
   const bool ok = det > 0.0f && finite_(det) && finite_(t) && !(bound > REROUTE_REL * det) && z[0] > 0.0f &&
                   c[2].hi + c[2].lo > 0.0f;
-  if (ok) scale_comp(c, t, x);
+  scale_comp(c, t, x);
   return ok;
 }
 
@@ -289,22 +291,31 @@ PX_HD DW<double> sum3_exact(double p1, double p2, double p3) {
   return DW<double>{s, e1 + e2};
 }
 
+// The cofactors that enter the determinant (a_c, b_c, c_c) and the leading
+// minor f_c of the positive-definiteness check are kept as hi + lo; d_c and
+// e_c only scale into inverse entries, whose FP32 rounding covers the error
+// of a plain sum of the three exact products (at most 2u sum|products|,
+// below 7e-8 of the inverse's norm for condition numbers up to 1e8), so
+// they are summed plainly (lo = 0) at a third of the operations.
+PX_HD DW<double> sum3_plain(double p1, double p2, double p3) { return DW<double>{(p1 + p2) + p3, 0.0}; }
+
 PX_HD void cofactors_widened(const double z[9], DW<double> c[9]) {
   const double a = z[0], d = z[1], f = z[2], br = z[3], bi = z[4], cr = z[5], ci = z[6], er = z[7], ei = z[8];
   c[0] = sum3_exact(d * f, -(er * er), -(ei * ei));
-  c[1] = sum3_exact(a * f, -(cr * cr), -(ci * ci));
+  c[1] = sum3_plain(a * f, -(cr * cr), -(ci * ci));
   c[2] = sum3_exact(a * d, -(br * br), -(bi * bi));
   c[3] = sum3_exact(cr * er, ci * ei, -(br * f));
   c[4] = sum3_exact(ci * er, -(cr * ei), -(bi * f));
   c[5] = sum3_exact(br * er, -(bi * ei), -(cr * d));
   c[6] = sum3_exact(br * ei, bi * er, -(ci * d));
-  c[7] = sum3_exact(cr * br, ci * bi, -(a * er));
-  c[8] = sum3_exact(ci * br, -(cr * bi), -(a * ei));
+  c[7] = sum3_plain(cr * br, ci * bi, -(a * er));
+  c[8] = sum3_plain(ci * br, -(cr * bi), -(a * ei));
 }
 
 // adjugate_comp_reroute: the FP64 recompute of one pixel, rounded to FP32:
 // exact-product cofactors as above, then the compensated determinant, the
-// one division and the scaling of the FP64 compensated form.
+// one division and the scaling of the FP64 compensated form (plain for the
+// plainly summed cofactors).
 PX_HD int adjugate_comp_reroute(const float z[9], float x[9], float& det) {
   double zd[9], xd[9], dd;
 #pragma unroll
@@ -318,6 +329,9 @@ PX_HD int adjugate_comp_reroute(const float z[9], float x[9], float& det) {
     dd = det_comp(zd, c, no_rerr, bound);
     const double t = 1.0 / dd;
     scale_comp(c, t, xd);
+    xd[1] = c[1].hi * t;  // the plainly summed cofactors: no low word
+    xd[7] = c[7].hi * t;
+    xd[8] = c[8].hi * t;
     st = classify(dd, t, zd[0], c[2].hi + c[2].lo);
   }
 #pragma unroll

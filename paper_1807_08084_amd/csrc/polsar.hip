@@ -569,6 +569,17 @@ std::map<std::tuple<int, int, int, int>, polsar_launch> g_cfg;
 // in 128-lane blocks, at most 5 per CU, ran the FP32 fused forward+backward
 // 9-16% faster than the 4096x4096 image's shape, which is 4% faster there.
 constexpr int64_t WISHART_SMALL = int64_t(1) << 23;
+// Images of at least this many pixels take the inverse kernel's launch from
+// op 6 of the table instead of op 0.  On an 8192x8192 image whose pixels are
+// a fifth recomputed in FP64 the FP32 compensated kernel with 8-byte
+// accesses ran 15% below its best shape (16-byte accesses in 128-lane
+// blocks, at most 8 per CU: four pixels per lane fill the wave's FP64 queue
+// twice as well as two), which stays within 3-5% of the best on an
+// 8192x8192 image with almost no recomputes; on 4096x4096 images 8-byte
+// accesses are 2-5% faster.  The Cholesky forms and the FP32-I/O FP64
+// adjugate take the joint best of both 8192x8192 images (1-2% over their
+// op-0 shapes); the other forms keep their op-0 shapes.
+constexpr int64_t INV_DET_LARGE = int64_t(1) << 25;
 
 polsar_launch default_launch(int op, int dtype, int method, int prec) {
   const bool f64 = dtype == POLSAR_F64, chol = method == POLSAR_CHOLESKY;
@@ -583,6 +594,13 @@ polsar_launch default_launch(int op, int dtype, int method, int prec) {
       return f64 ? polsar_launch{256, 1, 2, 1, 16, 6} : polsar_launch{256, 1, 16, 1, 16, 0};
     case 4:  // copy probe: few waves in flight stream best
       return polsar_launch{64, 1, 0, 1, 16, 5};
+    case 6:  // the inverse kernel on images of at least INV_DET_LARGE pixels
+      if (f64) break;
+      if (!chol && prec == POLSAR_COMPENSATED) return polsar_launch{128, 1, 0, 1, 16, 8};
+      if (!chol && prec == POLSAR_WIDE) return polsar_launch{64, 1, 0, 1, 16, 5};
+      if (chol && prec == POLSAR_PLAIN) return polsar_launch{128, 1, 0, 1, 16, 3};
+      if (chol && prec == POLSAR_COMPENSATED) return polsar_launch{128, 1, 0, 1, 16, 8};
+      break;
     default:
       break;
   }
@@ -631,7 +649,7 @@ polsar_launch get_cfg(int op, int dtype, int method, int prec) {
 
 bool valid_launch(const polsar_launch& c, int op) {
   if (c.block != 64 && c.block != 128 && c.block != 256) return false;
-  if (c.unroll != 1 && c.unroll != 2 && !(op == 0 && c.unroll == 4)) return false;
+  if (c.unroll != 1 && c.unroll != 2 && !((op == 0 || op == 6) && c.unroll == 4)) return false;
   if ((op == 2 || op == 3 || op == 4) && c.unroll != 1) return false;
   if (op == 4 && c.grid_per_cu != 0) return false;
   if (op == 3 && c.grid_per_cu == 0) return false;
@@ -652,6 +670,23 @@ int device_cus() {
     cached[dev] = cu;
   }
   return cached[dev];
+}
+
+// Blocks of a launch over `tiles` tiles.  Each wave adds its status tallies
+// to the caller's three counters with one atomic per counter when it ends;
+// with one tile per block that puts hundreds of thousands of atomics on the
+// same three addresses (6.1 ms against 0.88 ms for the FP32 compensated
+// inverse of an 8192x8192 image), so calls that ask for counters stride a
+// grid of at most COUNTER_GRID_PER_CU blocks per CU over the tiles instead.
+// Pixels are independent and the Wishart partial sums are kept per tile, so
+// results do not depend on the grid.
+constexpr int COUNTER_GRID_PER_CU = 16;
+int64_t launch_grid(const polsar_launch& c, int64_t tiles, bool counters) {
+  int gpc = c.grid_per_cu;
+  if (counters && (gpc == 0 || gpc > COUNTER_GRID_PER_CU)) gpc = COUNTER_GRID_PER_CU;
+  int64_t grid = tiles;
+  if (gpc > 0) grid = std::min<int64_t>(grid, (int64_t)gpc * device_cus());
+  return grid;
 }
 
 inline size_t esize(int dtype) { return dtype == POLSAR_F64 ? 8 : 4; }
@@ -713,8 +748,7 @@ hipError_t dispatch_inv_det_v(const polsar_launch& c, InvDetArgs& a, hipStream_t
   const int unroll = inv_det_unroll<T, OP, V>(c);
   const int64_t per_tile = (int64_t)c.block * unroll;
   a.tiles = std::max<int64_t>(1, (a.nvec + per_tile - 1) / per_tile);
-  int64_t grid = a.tiles;
-  if (c.grid_per_cu > 0) grid = std::min<int64_t>(grid, (int64_t)c.grid_per_cu * device_cus());
+  const int64_t grid = launch_grid(c, a.tiles, a.counters != nullptr);
   if (unroll == 1) return go_inv_det<T, OP, V, 1>(c, grid, a, s);
   if constexpr (OP == ADJ_COMP && std::is_same<T, float>::value) {
     return go_inv_det<T, OP, V, 2>(c, grid, a, s);
@@ -805,8 +839,7 @@ template <class T, int OP, int V>
 hipError_t dispatch_multilook_v(const polsar_launch& c, MultilookArgs& a, hipStream_t s) {
   a.o.nvec = a.o.n / V;
   a.o.tiles = std::max<int64_t>(1, (a.o.nvec + c.block - 1) / c.block);
-  int64_t grid = a.o.tiles;
-  if (c.grid_per_cu > 0) grid = std::min<int64_t>(grid, (int64_t)c.grid_per_cu * device_cus());
+  const int64_t grid = launch_grid(c, a.o.tiles, a.o.counters != nullptr);
   const size_t lds = launch_lds(c, 0);
   if (c.nontemporal)
     hipLaunchKernelGGL((k_multilook<T, OP, V, true>), dim3((unsigned)grid), dim3(c.block), lds, s, a);
@@ -885,8 +918,7 @@ template <class T, int OP, int V>
 hipError_t dispatch_block_v(const polsar_launch& c, BlockArgs& a, hipStream_t s) {
   a.o.nvec = a.o.n / V;
   a.o.tiles = std::max<int64_t>(1, (a.o.nvec + c.block - 1) / c.block);
-  int64_t grid = a.o.tiles;
-  if (c.grid_per_cu > 0) grid = std::min<int64_t>(grid, (int64_t)c.grid_per_cu * device_cus());
+  const int64_t grid = launch_grid(c, a.o.tiles, a.o.counters != nullptr);
   const size_t lds = launch_lds(c, 0);
   if (c.nontemporal)
     hipLaunchKernelGGL((k_blockdiag<T, OP, V, true>), dim3((unsigned)grid), dim3(c.block), lds, s, a);
@@ -935,8 +967,7 @@ hipError_t dispatch_wishart_v(const polsar_launch& c, WishartArgs& a, hipStream_
   a.nvec = a.n / V;
   const int64_t per_tile = (int64_t)c.block * c.unroll;
   a.tiles = std::max<int64_t>(1, (a.nvec + per_tile - 1) / per_tile);
-  int64_t grid = a.tiles;
-  if (c.grid_per_cu > 0) grid = std::min<int64_t>(grid, (int64_t)c.grid_per_cu * device_cus());
+  const int64_t grid = launch_grid(c, a.tiles, a.counters != nullptr);
   return c.unroll == 1 ? go_wishart<T, V, 1>(c, grid, a, s) : go_wishart<T, V, 2>(c, grid, a, s);
 }
 
@@ -992,14 +1023,16 @@ int polsar_device_compute_units(int* cus) {
 
 int polsar_wishart_launch_op(int64_t n) { return n < WISHART_SMALL ? 5 : 1; }
 
+int polsar_inv_det_launch_op(int64_t n) { return n >= INV_DET_LARGE ? 6 : 0; }
+
 int polsar_get_launch(int op, int dtype, int method, int precision, polsar_launch* out) {
-  if (!out || op < 0 || op > 5) return POLSAR_E_ARG;
+  if (!out || op < 0 || op > 6) return POLSAR_E_ARG;
   *out = get_cfg(op, dtype, method, precision);
   return POLSAR_OK;
 }
 
 int polsar_set_launch(int op, int dtype, int method, int precision, const polsar_launch* cfg) {
-  if (!cfg || op < 0 || op > 5 || !valid_launch(*cfg, op)) return POLSAR_E_ARG;
+  if (!cfg || op < 0 || op > 6 || !valid_launch(*cfg, op)) return POLSAR_E_ARG;
   std::lock_guard<std::mutex> g(g_mu);
   g_cfg[std::make_tuple(op, dtype, method, precision)] = *cfg;
   return POLSAR_OK;
@@ -1012,7 +1045,7 @@ int polsar_inv_det(int dtype, int method, int precision, int64_t n, const void* 
   int r = prepare_inv_det(dtype, method, precision, n, z, z_pitch, inv, inv_pitch, det, status, counters, a, vec);
   if (r) return r;
   if (n == 0) return POLSAR_OK;
-  const polsar_launch c = get_cfg(0, dtype, method, precision);
+  const polsar_launch c = get_cfg(polsar_inv_det_launch_op(n), dtype, method, precision);
   if (launch_inv_det(dtype, op_code(method, precision), c, vec, a, (hipStream_t)stream) != hipSuccess)
     return POLSAR_E_HIP;
   return POLSAR_OK;
@@ -1249,7 +1282,7 @@ int polsar_autotune_inv_det(int dtype, int method, int precision, int64_t n, con
     if (e.first < win_ms) { win_ms = e.first; win = e.second; }
   {
     std::lock_guard<std::mutex> g(g_mu);
-    g_cfg[std::make_tuple(0, dtype, method, precision)] = win;
+    g_cfg[std::make_tuple(polsar_inv_det_launch_op(n), dtype, method, precision)] = win;
   }
   if (best) *best = win;
   if (best_ms) *best_ms = win_ms;
@@ -1382,7 +1415,7 @@ int polsar_streamer_run(polsar_streamer* s, int64_t n, const void* z, int64_t z_
     if (inv && overlap(span(inv, 9, inv_pitch, n, es), rz)) return POLSAR_E_ALIAS;
     if (det && overlap(span(det, 1, n, n, es), rz)) return POLSAR_E_ALIAS;
   }
-  const polsar_launch c = get_cfg(0, s->dtype, s->method, s->precision);
+  const polsar_launch c = get_cfg(polsar_inv_det_launch_op(s->chunk), s->dtype, s->method, s->precision);
   const int op = op_code(s->method, s->precision);
   const size_t P = (size_t)s->pitch * es;
   hipError_t e = hipSuccess;

@@ -249,9 +249,11 @@ def workspace_bytes(dtype: torch.dtype, n: int) -> int:
 
 def wishart_loglik(sigma: torch.Tensor, z: torch.Tensor, n_looks: float, *, forward: bool = True,
                    backward: bool = False, grad_loss: torch.Tensor | None = None, ell: bool = False,
-                   counters: torch.Tensor | None = None, workspace: torch.Tensor | None = None, stream=None):
+                   counters: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+                   grad: torch.Tensor | None = None, stream=None):
     """L = sum N (ln det S + tr(S^-1 Z)) and/or its packed gradient.
 
+    ``grad``: planes to write the gradient into (else new ones).
     Returns (loss 0-d float64 GPU tensor or None, grad or None, ell or None).
     """
     if sigma.dtype != z.dtype:
@@ -265,7 +267,12 @@ def wishart_loglik(sigma: torch.Tensor, z: torch.Tensor, n_looks: float, *, forw
     if mode == 0:
         raise ValueError("nothing to do")
     loss = torch.empty((), dtype=torch.float64, device=sigma.device) if forward else None
-    grad = empty_planes(9, sigma.shape[1:], sigma.dtype, sigma.device) if backward else None
+    if not backward:
+        grad = None
+    elif grad is None:
+        grad = empty_planes(9, sigma.shape[1:], sigma.dtype, sigma.device)
+    elif grad.dtype != sigma.dtype or grad[0].numel() != n:
+        raise ValueError("grad must match sigma")
     gp = _planes(grad, "grad")[1] if grad is not None else 0
     el = torch.empty(sigma.shape[1:], dtype=sigma.dtype, device=sigma.device) if (ell and forward) else None
     wsb = workspace_bytes(sigma.dtype, n) if forward else 0
@@ -329,6 +336,11 @@ def wishart_launch_op(n: int) -> int:
     return int(L.lib().polsar_wishart_launch_op(int(n)))
 
 
+def inv_det_launch_op(n: int) -> int:
+    """The launch-table op (0, or 6 for large images) of an inverse call on n pixels."""
+    return int(L.lib().polsar_inv_det_launch_op(int(n)))
+
+
 def set_launch(op: int, dtype: torch.dtype, method: str, precision: str, cfg: dict) -> None:
     c = L.Launch(**cfg)
     d = L.F32 if dtype == torch.float32 else L.F64
@@ -338,7 +350,8 @@ def set_launch(op: int, dtype: torch.dtype, method: str, precision: str, cfg: di
 
 def autotune_inv_det(z: torch.Tensor, method: str = "adjugate", precision: str = "compensated",
                      reps: int = 5, stream=None) -> tuple[dict, float]:
-    """Time every launch configuration on z (scratch outputs), install the best."""
+    """Time every launch configuration on z (scratch outputs), install the best
+    in the table entry that calls of this size use (inv_det_launch_op)."""
     dt = _dtype_code(z)
     n, zp = _planes(z, "z")
     inv = torch.empty_like(z, memory_format=torch.contiguous_format)

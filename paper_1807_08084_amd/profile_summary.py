@@ -1,7 +1,7 @@
 """Summarise rocprofv3 result databases (SQLite) into short text records.
 
     python -m paper_1807_08084_amd.profile_summary trace <kt_results.db> <out.txt> "<command>"
-    python -m paper_1807_08084_amd.profile_summary traffic <fetch.db> <write.db> <out.txt> "<commands>"
+    python -m paper_1807_08084_amd.profile_summary traffic <fetch.db> <write.db> <out.txt> "<commands>" [n_px] [label]
     python -m paper_1807_08084_amd.profile_summary counters <pmc.db> <out.txt> "<command>"
     python -m paper_1807_08084_amd.profile_summary traffic_rows <fetch.db> <write.db> <out.txt> "<commands>"
 
@@ -58,9 +58,12 @@ def _counter(db: str, counter: str, main_grid: bool = False):
     return {k: statistics.mean(max(by.values(), key=len)) for k, by in agg.items()}
 
 
-def traffic(fetch_db: str, write_db: str, out: str, command: str, n_px: int = 4096 * 4096) -> None:
-    f = _counter(fetch_db, "FETCH_SIZE")
-    w = _counter(write_db, "WRITE_SIZE")
+def traffic(fetch_db: str, write_db: str, out: str, command: str, n_px: int = 4096 * 4096,
+            label: str = "4096x4096 image") -> None:
+    """HBM bytes per launch of the FP32 compensated inverse kernel over an
+    n_px-pixel image (its dispatches at the most frequent grid size)."""
+    f = _counter(fetch_db, "FETCH_SIZE", main_grid=True)
+    w = _counter(write_db, "WRITE_SIZE", main_grid=True)
     def one_plane_copy(k):  # k_copy<float, V, 1, 1[, NT]>
         args = k[k.find("<") + 1:k.rfind(">")].split(", ")
         return k.startswith("k_copy<float,") and args[2:4] == ["1", "1"]
@@ -73,7 +76,7 @@ def traffic(fetch_db: str, write_db: str, out: str, command: str, n_px: int = 40
     wr = w[kern] * 1024 * w_scale
     alg_rd, alg_wr = 36 * n_px, 40 * n_px
     with open(out, "w") as fh:
-        fh.write("# HBM traffic of the FP32 compensated adjugate inverse kernel, 4096x4096 image\n")
+        fh.write(f"# HBM traffic of the FP32 compensated adjugate inverse kernel ({kern}), {label}\n")
         fh.write(f"# command: {command}\n")
         fh.write(f"# FETCH_SIZE probe {f[probe]:.1f} KiB for {probe_bytes} B read  -> scale {f_scale:.5f}\n")
         fh.write(f"# WRITE_SIZE probe {w[probe]:.1f} KiB for {probe_bytes} B written -> scale {w_scale:.5f}\n")
@@ -81,6 +84,7 @@ def traffic(fetch_db: str, write_db: str, out: str, command: str, n_px: int = 40
         fh.write(f"# read {rd:.0f} B (algorithmic {alg_rd}, ratio {rd / alg_rd:.5f}); "
                  f"write {wr:.0f} B (algorithmic {alg_wr}, ratio {wr / alg_wr:.5f})\n")
         fh.write(f"kernel = k_inv_det<float, ADJ_COMP>\n")
+        fh.write(f"pixels = {n_px}\n")
         fh.write(f"source_hash = {source_hash()}\n")
         fh.write(f"read_bytes_per_launch = {rd:.0f}\n")
         fh.write(f"write_bytes_per_launch = {wr:.0f}\n")
@@ -161,8 +165,9 @@ if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "counters":
-        counters(sys.argv[2], sys.argv[3], sys.argv[4])
+        counters(sys.argv[2], sys.argv[3], sys.argv[4], *([int(sys.argv[5])] if len(sys.argv) > 5 else []))
     elif sys.argv[1] == "traffic_rows":
         traffic_rows(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
     else:
-        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5],
+                *([int(sys.argv[6])] if len(sys.argv) > 6 else []), *sys.argv[7:8])

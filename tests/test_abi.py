@@ -117,10 +117,13 @@ def test_launch_table(lib):
     assert lib.polsar_get_launch(4, L.F32, 0, 0, ctypes.byref(got)) == L.OK
     assert got.unroll == 1 and got.grid_per_cu == 0
     assert lib.polsar_set_launch(4, L.F32, 0, 0, ctypes.byref(good)) == L.E_ARG
-    # op 5, the Wishart kernel on small images, and the op a call of n pixels uses;
-    # op 6 does not exist
+    # op 5, the Wishart kernel on small images, op 6, the inverse on large
+    # images, and the op a call of n pixels uses; op 7 does not exist
     assert lib.polsar_get_launch(5, L.F32, 0, 0, ctypes.byref(got)) == L.OK
-    assert lib.polsar_get_launch(6, L.F32, 0, 0, ctypes.byref(got)) == L.E_ARG
+    assert lib.polsar_get_launch(6, L.F32, L.ADJUGATE, L.COMPENSATED, ctypes.byref(got)) == L.OK
+    assert lib.polsar_get_launch(7, L.F32, 0, 0, ctypes.byref(got)) == L.E_ARG
+    assert lib.polsar_inv_det_launch_op(8192 * 8192) == 6 and lib.polsar_inv_det_launch_op(4096 * 4096) == 0
+    assert lib.polsar_inv_det_launch_op((1 << 25) - 1) == 0 and lib.polsar_inv_det_launch_op(1 << 25) == 6
     assert lib.polsar_wishart_launch_op(2048 * 2048) == 5 and lib.polsar_wishart_launch_op(4096 * 4096) == 1
     assert lib.polsar_wishart_launch_op((1 << 23) - 1) == 5 and lib.polsar_wishart_launch_op(1 << 23) == 1
 

@@ -143,6 +143,7 @@ def test_precision_workload(ops):
                                ("f32_cholesky_plain", zt32, "32", "cholesky", "plain"),
                                ("f32_cholesky_fallback", zt32, "32", "cholesky", "compensated"),
                                ("f32_adjugate_wide", zt32, "32", "adjugate", "wide"),
+                               ("f32_cholesky_wide", zt32, "32", "cholesky", "wide"),
                                ("f64_adjugate_plain", zt64, "64", "adjugate", "plain"),
                                ("f64_cholesky_plain", zt64, "64", "cholesky", "plain"),
                                ("f64_adjugate_compensated", zt64, "64", "adjugate", "compensated")):
@@ -166,9 +167,13 @@ def test_precision_workload(ops):
             if not msk.any():
                 continue
             bar = 1e-12 if name.startswith("f64") else 2e-6 * lo
+            # the stated bar per pixel: FP32 2e-6 kappa; FP64 1e-12 (kappa <= 1e6 only)
+            pbar = np.full(int(msk.sum()), 1e-12) if name.startswith("f64") else 2e-6 * k[msk]
+            meets = bool(np.all(ei[msk] <= pbar) and np.all(ed[msk] <= pbar))
             r = report["decades"].setdefault(f"1e{d}", {})
             r[name] = {"n": int(msk.sum()), "inv_max": float(np.max(ei[msk])), "inv_p99": float(np.quantile(ei[msk], 0.99)),
-                       "det_max": float(np.max(ed[msk])), "bar_at_decade_low": bar}
+                       "det_max": float(np.max(ed[msk])), "det_p99": float(np.quantile(ed[msk], 0.99)),
+                       "bar_at_decade_low": bar, "meets_bar": meets}
         m32 = pd32 & (k32 >= lo) & (k32 < hi)
         report["decades"].setdefault(f"1e{d}", {})["f32_reroute_fraction"] = float(np.mean(g_st[m32] == 1)) if m32.any() else None
     if OUT:
@@ -176,7 +181,8 @@ def test_precision_workload(ops):
         with open(os.path.join(OUT, "precision_8192.json"), "w") as fh:
             json.dump(report, fh, indent=1)
     for dec, r in report["decades"].items():
-        log(f"kappa {dec}: " + ", ".join(f"{k} {v['inv_max']:.1e}" for k, v in r.items() if isinstance(v, dict)))
+        log(f"kappa {dec}: " + ", ".join(f"{k} {v['inv_max']:.1e}/{v['det_max']:.1e}{'' if v['meets_bar'] else '!'}"
+                                         for k, v in r.items() if isinstance(v, dict)))
 
 
 # ---------------------------------------------------------------- 2048^2 Wishart

@@ -47,14 +47,15 @@ def test_traffic_rows_scales_by_the_probe_and_takes_the_main_grid(tmp_path):
 def test_bench_reads_traffic_only_for_the_current_sources(tmp_path, monkeypatch):
     rec = tmp_path / "profiles"
     rec.mkdir()
-    text = ("# header\nkernel = k_inv_det<float, ADJ_COMP>\nsource_hash = {h}\n"
+    text = ("# header\nkernel = k_inv_det<float, ADJ_COMP>\npixels = 16777216\nsource_hash = {h}\n"
             "bytes_per_launch = 1275000000\n")
     monkeypatch.setattr(bench, "HERE", str(tmp_path))
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "abc")
-    (rec / "hbm_traffic_inv_det_4096.txt").write_text(text.format(h="abc"))
+    (rec / bench.TRAFFIC_RECORD).write_text(text.format(h="abc"))
     assert bench.traffic_from_profiles("k_inv_det<float, ADJ_COMP>", N_PX) == 1275000000.0
     assert bench.traffic_from_profiles("k_inv_det<double, ADJ_COMP>", N_PX) is None
-    (rec / "hbm_traffic_inv_det_4096.txt").write_text(text.format(h="stale"))
+    assert bench.traffic_from_profiles("k_inv_det<float, ADJ_COMP>", 4 * N_PX) is None  # another image
+    (rec / bench.TRAFFIC_RECORD).write_text(text.format(h="stale"))
     assert bench.traffic_from_profiles("k_inv_det<float, ADJ_COMP>", N_PX) is None
-    os.remove(rec / "hbm_traffic_inv_det_4096.txt")
+    os.remove(rec / bench.TRAFFIC_RECORD)
     assert bench.traffic_from_profiles("k_inv_det<float, ADJ_COMP>", N_PX) is None
