@@ -188,7 +188,9 @@ typedef enum { POLSAR_FWD = 1, POLSAR_BWD = 2, POLSAR_FWD_BWD = 3 } polsar_pass;
  *   grad       out (BWD, FWD_BWD): 9 planes, pitch g_pitch
  *   workspace  device scratch of at least polsar_wishart_workspace_bytes(n)
  *              bytes (FWD, FWD_BWD), 8-byte aligned; holds per-tile FP64
- *              partial sums, reduced in a fixed order (deterministic).
+ *              partial sums, which a second kernel adds in tile order
+ *              (deterministic).  Calls that share a workspace must not
+ *              overlap in time (one stream, or synchronised streams).
  *   counters   as for polsar_inv_det ([not_pd, 0, nonfinite] for S).
  * Launch shape: op 1 of polsar_get_launch, op 5 below 2^23 pixels (see
  * polsar_wishart_launch_op); the loss's summation order follows the tiles,

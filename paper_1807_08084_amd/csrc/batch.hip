@@ -217,7 +217,8 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs a, const ImgDesc* __res
 }
 
 // One block per image: fixed-order sum of its tiles' partials into loss.
-__global__ __launch_bounds__(256) void k_batch_reduce(const ImgDesc* __restrict__ img, const double* __restrict__ partial) {
+__global__ __launch_bounds__(REDUCE_BLOCK) void k_batch_reduce(const ImgDesc* __restrict__ img,
+                                                                const double* __restrict__ partial) {
   const ImgDesc& d = img[blockIdx.x];
   const double s = strided_sum(partial + d.tile0, d.ntiles);
   if (threadIdx.x == 0 && d.loss) *d.loss = s;
@@ -283,7 +284,7 @@ hipError_t enqueue(const polsar_batch* b, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (b->ops & POLSAR_OP_WISHART_FWD) {
-    hipLaunchKernelGGL(k_batch_reduce, dim3(b->count), dim3(256), 0, s, (const ImgDesc*)b->d_img,
+    hipLaunchKernelGGL(k_batch_reduce, dim3(b->count), dim3(REDUCE_BLOCK), 0, s, (const ImgDesc*)b->d_img,
                        (const double*)b->d_partial);
     e = hipGetLastError();
   }

@@ -232,10 +232,15 @@ inline size_t comp_queue_bytes(int block, int slots) {
   return entries * (QUEUE_WORDS * sizeof(float) + 1);
 }
 
-// Deterministic block sum of one double per lane; result valid in lane 0
-// of wave 0.  Order: fixed butterfly within each wave, then waves in order.
+// Lanes of the fixed-order reduction kernels (the per-call Wishart loss and
+// the batch's per-image losses use the same, so their orders agree).
+constexpr int REDUCE_BLOCK = 1024;
+
+// Deterministic block sum of one double per lane (blocks of up to 1024
+// lanes); result valid in lane 0 of wave 0.  Order: fixed butterfly within
+// each wave, then waves in order.
 __device__ __forceinline__ double block_sum(double v) {
-  __shared__ double wsum[4];
+  __shared__ double wsum[16];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   const int w = threadIdx.x >> 6;

@@ -525,8 +525,10 @@ __global__ __launch_bounds__(256) void k_wishart(WishartArgs a) {
   if (a.counters) flush_counters(a.counters, c0, 0u, c2);
 }
 
-// Fixed-order sum of `count` partials into *out (one block of 256 lanes).
-__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ partial, int64_t count,
+// Fixed-order sum of `count` partials into *out (one block of REDUCE_BLOCK
+// lanes: the 16,384 partials of a 2048x2048 FP32 call take one round of
+// sixteen loads per lane).
+__global__ __launch_bounds__(REDUCE_BLOCK) void k_reduce(const double* __restrict__ partial, int64_t count,
                                                 double* __restrict__ out) {
   const double s = strided_sum(partial, count);
   if (threadIdx.x == 0) *out = s;
@@ -962,11 +964,20 @@ hipError_t go_wishart(const polsar_launch& c, int64_t grid, WishartArgs& a, hipS
   return hipGetLastError();
 }
 
+// Pixels per access of a Wishart launch, and its tiles (one partial sum each).
+int wishart_vector(const polsar_launch& c, bool vec, size_t es) {
+  const int vw = (int)(16 / es);
+  return !vec ? 1 : (c.vector_bytes == 8 ? vw / 2 : vw);
+}
+int64_t wishart_tiles(const polsar_launch& c, int v, int64_t n) {
+  const int64_t per_tile = (int64_t)c.block * c.unroll;
+  return std::max<int64_t>(1, (n / v + per_tile - 1) / per_tile);
+}
+
 template <class T, int V>
 hipError_t dispatch_wishart_v(const polsar_launch& c, WishartArgs& a, hipStream_t s) {
   a.nvec = a.n / V;
-  const int64_t per_tile = (int64_t)c.block * c.unroll;
-  a.tiles = std::max<int64_t>(1, (a.nvec + per_tile - 1) / per_tile);
+  a.tiles = wishart_tiles(c, V, a.n);
   const int64_t grid = launch_grid(c, a.tiles, a.counters != nullptr);
   return c.unroll == 1 ? go_wishart<T, V, 1>(c, grid, a, s) : go_wishart<T, V, 2>(c, grid, a, s);
 }
@@ -1161,10 +1172,19 @@ size_t polsar_wishart_workspace_bytes(int dtype, int64_t n) {
   return (size_t)max_wishart_partials(n) * sizeof(double);
 }
 
-int polsar_wishart_loglik(int dtype, int pass, int64_t n, const void* sigma, int64_t s_pitch, const void* z,
-                          int64_t z_pitch, double n_looks, double* loss, void* ell, const double* grad_loss,
-                          void* grad, int64_t g_pitch, void* workspace, size_t ws_bytes,
-                          unsigned long long* counters, void* stream) {
+}  // extern "C"
+
+// polsar_wishart_loglik and its allocation-free variant: validation and
+// launch with the per-tile partial sums at `ws` (ws_words words of 8 bytes):
+// the caller's workspace (its size is checked against the largest tile count
+// of any launch), or, when fixed_ws is given, the library's fixed scratch of
+// ws_words words (checked against this launch's tile count), whose device
+// address fixed_ws returns once every argument has passed validation.
+int polsar_wishart_call(int dtype, int pass, int64_t n, const void* sigma, int64_t s_pitch, const void* z,
+                        int64_t z_pitch, double n_looks, double* loss, void* ell, const double* grad_loss, void* grad,
+                        int64_t g_pitch, double* ws, int64_t ws_words, int (*fixed_ws)(double**),
+                        unsigned long long* counters, void* stream) {
+  const bool ws_user = fixed_ws == nullptr;
   if (dtype != POLSAR_F32 && dtype != POLSAR_F64) return POLSAR_E_ARG;
   if (pass != POLSAR_FWD && pass != POLSAR_BWD && pass != POLSAR_FWD_BWD) return POLSAR_E_ARG;
   if (n < 0 || !(n_looks > 0.0)) return POLSAR_E_ARG;
@@ -1179,9 +1199,9 @@ int polsar_wishart_loglik(int dtype, int pass, int64_t n, const void* sigma, int
   if (ell && ((uintptr_t)ell % es)) return POLSAR_E_ALIGN;
   if (counters && ((uintptr_t)counters % 8)) return POLSAR_E_ALIGN;
   if (bwd && (r = check_planes(grad, g_pitch, n, es))) return r;
-  if (fwd && n > 0) {
-    if (!workspace || ws_bytes < polsar_wishart_workspace_bytes(dtype, n)) return POLSAR_E_WORKSPACE;
-    if ((uintptr_t)workspace % 8) return POLSAR_E_ALIGN;
+  if (fwd && n > 0 && ws_user) {
+    if (!ws || ws_words < max_wishart_partials(n)) return POLSAR_E_WORKSPACE;
+    if ((uintptr_t)ws % 8) return POLSAR_E_ALIGN;
   }
   if (n > 0) {
     const Range rs = span(sigma, 9, s_pitch, n, es), rz = span(z, 9, z_pitch, n, es);
@@ -1195,27 +1215,41 @@ int polsar_wishart_loglik(int dtype, int pass, int64_t n, const void* sigma, int
         return POLSAR_E_ALIAS;
     }
   }
+  const bool vec = n > 0 && vec_ok(sigma, s_pitch, es) && vec_ok(z, z_pitch, es) &&
+                   (!bwd || vec_ok(grad, g_pitch, es)) && (!(fwd && ell) || vec_ok(ell, 0, es));
+  const polsar_launch c = get_cfg(polsar_wishart_launch_op(n), dtype, 0, 0);
+  if (fwd && n > 0 && !ws_user) {
+    if (wishart_tiles(c, wishart_vector(c, vec, es), n) > ws_words) return POLSAR_E_WORKSPACE;
+    if ((r = fixed_ws(&ws))) return r;
+  }
   hipStream_t s = (hipStream_t)stream;
   if (n == 0) {
     if (fwd) {
       // an empty sum is zero: reduce zero partials
-      hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, (const double*)workspace, (int64_t)0, loss);
+      hipLaunchKernelGGL(k_reduce, dim3(1), dim3(REDUCE_BLOCK), 0, s, (const double*)nullptr, (int64_t)0, loss);
       if (hipGetLastError() != hipSuccess) return POLSAR_E_HIP;
     }
     return POLSAR_OK;
   }
-  WishartArgs a{sigma, s_pitch, z, z_pitch, n_looks, fwd ? ell : nullptr, (double*)workspace, grad_loss,
+  WishartArgs a{sigma, s_pitch, z, z_pitch, n_looks, fwd ? ell : nullptr, fwd ? ws : nullptr, grad_loss,
                 bwd ? grad : nullptr, g_pitch, counters, n, 0, 0, fwd ? 1 : 0, bwd ? 1 : 0};
-  const bool vec = vec_ok(sigma, s_pitch, es) && vec_ok(z, z_pitch, es) && (!bwd || vec_ok(grad, g_pitch, es)) &&
-                   (!(fwd && ell) || vec_ok(ell, 0, es));
-  const polsar_launch c = get_cfg(polsar_wishart_launch_op(n), dtype, 0, 0);
   hipError_t e = dtype == POLSAR_F32 ? dispatch_wishart<float>(c, vec, a, s) : dispatch_wishart<double>(c, vec, a, s);
   if (e != hipSuccess) return POLSAR_E_HIP;
   if (fwd) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, (const double*)workspace, a.tiles, loss);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(REDUCE_BLOCK), 0, s, (const double*)ws, a.tiles, loss);
     if (hipGetLastError() != hipSuccess) return POLSAR_E_HIP;
   }
   return POLSAR_OK;
+}
+
+extern "C" {
+
+int polsar_wishart_loglik(int dtype, int pass, int64_t n, const void* sigma, int64_t s_pitch, const void* z,
+                          int64_t z_pitch, double n_looks, double* loss, void* ell, const double* grad_loss,
+                          void* grad, int64_t g_pitch, void* workspace, size_t ws_bytes,
+                          unsigned long long* counters, void* stream) {
+  return polsar_wishart_call(dtype, pass, n, sigma, s_pitch, z, z_pitch, n_looks, loss, ell, grad_loss, grad, g_pitch,
+                      (double*)workspace, (int64_t)(ws_bytes / sizeof(double)), nullptr, counters, stream);
 }
 
 int polsar_autotune_inv_det(int dtype, int method, int precision, int64_t n, const void* z, int64_t z_pitch,
