@@ -204,6 +204,26 @@ int polsar_wishart_loglik(int dtype, int pass, int64_t n,
                           unsigned long long* counters, void* stream);
 size_t polsar_wishart_workspace_bytes(int dtype, int64_t n);
 
+/* polsar_wishart_loglik without a workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the forward pass keeps its partial sums
+ * in a fixed array of this library, 8 MiB on each GPU it runs on,
+ * held until the process ends.  Arguments as for polsar_wishart_loglik;
+ * same kernels and launch, so the same results bit for bit.  The call
+ * allocates nothing (no hipMalloc, no library allocation).  The forward pass
+ * takes at most 2^20 tiles of the launch in use: at the default launches
+ * FP32 images of up to 2^28 pixels (2^30 with 16-byte aligned planes) and
+ * FP64 images of up to 2^27; beyond that POLSAR_E_WORKSPACE, before any HIP
+ * call.  Every call on
+ * one GPU shares its array: calls that overlap in time on one GPU (other
+ * streams, other host threads) race and must not be issued. */
+int polsar_wishart_loglik_noalloc(int dtype, int pass, int64_t n,
+                                  const void* sigma, int64_t s_pitch,
+                                  const void* z, int64_t z_pitch, double n_looks,
+                                  double* loss, void* ell, const double* grad_loss,
+                                  void* grad, int64_t g_pitch,
+                                  unsigned long long* counters, void* stream);
+
 /* Batched persistent launch over many images of uneven sizes: the paper's
  * closing section names, as future work, combining several matrix
  * inversions into a single inversion call; here one call (one graph launch)

@@ -68,6 +68,8 @@ def lib():
         L.polsar_nlm_wishart.argtypes = [i, i, i64, i64, i, d, d, vp, i64, vp, i64, vp, i64, vp, vp]
         L.polsar_wishart_loglik.argtypes = [i, i, i64, vp, i64, vp, i64, d, vp, vp, vp, vp, i64, vp, sz, vp, vp]
         L.polsar_wishart_workspace_bytes.argtypes = [i, i64]
+        L.polsar_wishart_loglik_noalloc.argtypes = [i, i, i64, vp, i64, vp, i64, ctypes.c_double, vp, vp, vp, vp,
+                                                    i64, vp, vp]
         L.polsar_wishart_workspace_bytes.restype = sz
         L.polsar_batch_create.argtypes = [ctypes.POINTER(Image), i, i, i, i, ctypes.c_uint, vp, vp, i,
                                           ctypes.POINTER(vp)]

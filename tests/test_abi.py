@@ -214,3 +214,17 @@ def test_nlm_argument_errors(lib):
     assert args(L.F32, 0, 10, (1 << 20) + 1, 3) == L.E_ARG
     assert nl(L.F32, 0, 10, 10, 3, 4.0, 16.0, FAKE, 100, FAKE2, 100, FAKE + 400, 100, None, None) == L.E_ALIAS
     assert args(L.F32, 0, 0, 10, 3) == L.OK                       # empty
+
+
+def test_wishart_noalloc_rejects_sizes_beyond_its_scratch(lib):
+    """2^20 + 1 tiles at the default launches (FP64: 128 pixels per tile;
+    FP32 with 16-byte aligned planes: 1024): one more than the fixed scratch
+    holds.  Rejected before any HIP call; nothing is launched."""
+    for dtype, n in ((L.F64, (1 << 27) + 128), (L.F32, (1 << 30) + 1024)):
+        rc = lib.polsar_wishart_loglik_noalloc(dtype, L.FWD, n, FAKE, n, FAKE2, n, 4.0, FAKE3, None, None, None, 0,
+                                               None, None)
+        assert rc == L.E_WORKSPACE
+    assert lib.polsar_wishart_loglik_noalloc(L.F32, 0, 100, FAKE, 100, FAKE2, 100, 4.0, FAKE3, None, None, None,
+                                             0, None, None) == L.E_ARG
+    assert lib.polsar_wishart_loglik_noalloc(L.F32, L.FWD, 100, FAKE, 100, FAKE2, 100, 4.0, None, None, None,
+                                             None, 0, None, None) == L.E_ARG
