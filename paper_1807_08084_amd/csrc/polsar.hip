@@ -1104,7 +1104,9 @@ int polsar_boxcar_inv_det(int dtype, int method, int precision, int64_t height, 
   if (height < 0 || width < 0 || radius < 0 || radius > BOX_MAX_R) return POLSAR_E_ARG;
   if (height > ((int64_t)1 << 24) || width > ((int64_t)1 << 24)) return POLSAR_E_ARG;
   const int64_t n = height * width;
-  if (n > ((int64_t)1 << 32)) return POLSAR_E_ARG;  // one block per 64 x 32 strip, 1-D grid
+  // one block per 64 columns of a strip of 32 or 64 rows: at most ~2^21
+  // blocks, a 1-D grid
+  if (n > ((int64_t)1 << 32)) return POLSAR_E_ARG;
   const size_t es = esize(dtype);
   if ((r = check_planes(s, s_pitch, n, es))) return r;
   if (z && (r = check_planes(z, z_pitch, n, es))) return r;

@@ -49,7 +49,10 @@ def _check_z(z_gpu, s_np, H, W, r, u, pixels=None):
     (torch.float32, "adjugate", "compensated"), (torch.float32, "cholesky", "plain"),
     (torch.float64, "adjugate", "compensated"), (torch.float64, "cholesky", "plain")])
 @pytest.mark.parametrize("H,W,r", [(37, 70, 3), (13, 129, 2), (9, 65, 1), (64, 4, 3), (5, 3, 3), (1, 100, 2),
-                                   (20, 20, 0), (70, 300, 2)])  # the last: 15 tiles, more than 8 and not a multiple
+                                   (20, 20, 0),
+                                   (70, 300, 2),   # 15 tiles: more than 8 and not a multiple
+                                   (130, 70, 3),   # crosses two boundaries of the 64-row strips
+                                   (70, 65, 1)])   # crosses two boundaries of the 32-row strips
 def test_boxcar_equals_two_step(ops, dtype, method, prec, H, W, r):
     s_np = _single_look(H, W, 11 + H)
     if dtype == torch.float32:
@@ -65,7 +68,11 @@ def test_boxcar_equals_two_step(ops, dtype, method, prec, H, W, r):
     s_h = st.cpu().numpy()
     c = ctr.cpu().numpy()
     assert c[0] == np.sum(s_h == 2) and c[1] == np.sum(s_h == 1) and c[2] == np.sum(s_h == 3)
-    if r == 0:  # one look: Z is S S^H rounded, singular to rounding; nothing more to compare
+    if r == 0:
+        # one look: Z = S S^H is rank one; rounded, the few matrices the
+        # oracle calls positive definite have kappa ~ 1e10 and more, where the
+        # rounding of Z itself decides the inverse: only Z and the two-step
+        # equality above are checkable
         return
     # against the oracle's inverse of its own Z (rounded to the storage type),
     # allowing for the distance between that Z and the kernel's
@@ -81,7 +88,10 @@ def test_boxcar_equals_two_step(ops, dtype, method, prec, H, W, r):
         tol = 64 * u * k * k
     tol = tol + 4 * k * delta
     sel = pd & (k * delta < 0.1)
-    assert sel.sum() >= 0.9 * pd.sum()
+    # every pixel the oracle calls positive definite is compared: on these
+    # inputs none is close enough to singular for the distance between the
+    # oracle's Z and the kernel's to matter
+    assert np.array_equal(sel, pd)
     e = oracle.inv_rel_err(to_np(inv).reshape(9, -1), ih, il)
     assert np.all(e[sel] <= tol[sel])
 

@@ -1,13 +1,35 @@
 """Block-diagonal (multifrequency) pixels and out-of-core streaming on the GPU:
-both must reproduce polsar_inv_det bitwise, and the block determinant
-product must match the oracle."""
+both reproduce polsar_inv_det bitwise, and both are checked against the
+oracle: each block's inverse and determinant and the determinant product
+(block-diagonal case of the Conclusion), and the streamed inverse and
+determinant of a host-resident image (Section 4's closing discussion)."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 from paper_1807_08084_amd import synth
-from _helpers import to_np
+from _helpers import to_np, tol_f32, tol_f64_comp
+
+
+def _against_oracle(z64, inv, det, dtype):
+    """FP64 results against the __float128 oracle at the FP64 bar (1e-12 up
+    to kappa 1e6); FP32 results against the FP64 oracle of the same stored
+    input at 2e-6 kappa.  z64: the stored input, widened exactly."""
+    k = oracle.kappa(z64)
+    assert np.all(oracle.pd_class(z64) == 0)
+    if dtype == torch.float64:
+        (ih, il), (dh, dl) = oracle.ge128(z64)
+        e_inv, e_det = oracle.inv_rel_err(inv, ih, il), oracle.det_rel_err(det, dh, dl)
+        tol = tol_f64_comp(k)
+    else:
+        inv_o, det_o = oracle.ge(z64)
+        e_inv, e_det = oracle.inv_rel_err(inv, inv_o), oracle.det_rel_err(det, det_o)
+        tol = tol_f32(k)
+    assert np.all(e_inv <= tol), (e_inv / tol).max()
+    assert np.all(e_det <= tol), (e_det / tol).max()
+    return e_inv.max(), e_det.max()
+
 
 pytestmark = pytest.mark.gpu
 
@@ -35,6 +57,7 @@ def test_blockdiag(ops, dtype, n_side):
     for b in range(3):
         ib, db, sb = ops.inv_det(z[9 * b:9 * b + 9], "adjugate", "compensated", status=True)
         assert torch.equal(inv[9 * b:9 * b + 9], ib) and torch.equal(bd[b], db)
+        _against_oracle(z_np[9 * b:9 * b + 9], to_np(inv[9 * b:9 * b + 9]).reshape(9, -1), to_np(bd[b]), dtype)
         _, (dh, _) = oracle.ge128(z_np[9 * b:9 * b + 9])
         prod_ref_hi *= dh
     assert torch.all(st <= 1)
@@ -57,6 +80,8 @@ def test_blockdiag(ops, dtype, n_side):
 def test_streamer_matches_device_path(ops, dtype):
     img = synth.make_image(1000, 1001, 4, (2, 2), (1e-3, 1.0), 9)
     z_np = img.planes.reshape(9, -1)
+    if dtype == torch.float32:
+        z_np = z_np.astype(np.float32).astype(np.float64)
     n = z_np.shape[1]
     zh = torch.empty((9, n), dtype=dtype, pin_memory=True)
     zh.copy_(torch.from_numpy(z_np))
@@ -70,3 +95,4 @@ def test_streamer_matches_device_path(ops, dtype):
     torch.cuda.synchronize()
     assert torch.equal(inv_h, inv_d.cpu()) and torch.equal(det_h, det_d.cpu()) and torch.equal(st_h, st_d.cpu())
     assert int(ctr[1].item()) == int((st_d == 1).sum().item())
+    _against_oracle(z_np, inv_h.numpy().astype(np.float64), det_h.numpy().astype(np.float64), dtype)

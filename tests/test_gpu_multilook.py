@@ -59,7 +59,7 @@ def test_fused_equals_two_step(ops, looks_img, dtype, method, prec):
         tol_f32(k) if prec == "compensated" else 64 * u * k * k)
     tol = tol + 4 * k * delta
     sel = k * delta < 0.1
-    assert sel.mean() > 0.99
+    assert sel.all()  # every pixel is compared (none is close enough to singular to be set aside)
     e = oracle.inv_rel_err(to_np(inv).reshape(9, -1), ih, il)
     assert np.all(e[sel] <= tol[sel])
 
