@@ -48,12 +48,15 @@ BYTES_PER_PX = {"f32": 76, "f64": 152}         # 9 planes in + 9 inverse planes 
 WISHART_BYTES_PER_PX = {"f32": 108, "f64": 216}  # fused fwd+bwd: S, Z in (72) + grad out (36)
 
 
+# the sources the inverse kernel (the step) is compiled from
+STEP_SOURCES = ("common.hpp", "pixel.hpp", "polsar.hip")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "paper_1807_08084_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(csrc, name), "rb").read())
+    for name in STEP_SOURCES:
+        h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -347,10 +350,26 @@ def scale_rows(torch, ops, dev, img, steps: int) -> dict:
     return rows
 
 
-def other_workloads(torch, ops, dev, steps):
-    """Each remaining workload timed on its own input (device time, data resident)."""
+OTHER_WORKLOADS = ("wishart", "batch", "paper")
+
+
+def other_workloads(torch, ops, dev, steps, which=OTHER_WORKLOADS, tune_launch=True):
+    """Each remaining workload timed on its own input (device time, data
+    resident); with tune_launch, again at the launch the tuner picks."""
     from paper_1807_08084_amd import synth, tune
     from paper_1807_08084_amd.batch import BatchPlan
+    res = {}
+    if "wishart" in which:
+        res.update(_wishart_workload(torch, ops, dev, steps, tune_launch))
+    if "batch" in which:
+        res.update(_batch_workload(torch, ops, dev, steps, tune_launch))
+    if "paper" in which:
+        res.update(_paper_workloads(torch, ops, dev))
+    return res
+
+
+def _wishart_workload(torch, ops, dev, steps, tune_launch):
+    from paper_1807_08084_amd import synth, tune
     res = {}
     # Wishart: 2048^2, N=8; fused forward + backward.  One image's inputs and
     # gradient (453 MB in FP32) fit largely in the 256 MB last-level cache
@@ -374,16 +393,24 @@ def other_workloads(torch, ops, dev, steps):
         steps_w = max(steps, 4 * copies)
         ms = time_calls(call, steps_w, copies, torch)
         res[f"wishart_2048_fwd_bwd_{tn}"] = rate_row(n, ms, bpp, input_copies=copies)
-        # again with the launch the Wishart tuner picks on this image
-        wop = ops.wishart_launch_op(n)
-        keep = ops.get_launch(wop, dt, "adjugate", "plain")
-        cfg, _ = tune.tune_wishart(sets[0][0], sets[0][1], 8.0, reps=10)
-        ms = time_calls(call, steps_w, copies, torch)
-        res[f"wishart_2048_fwd_bwd_{tn}_autotuned"] = rate_row(n, ms, bpp, input_copies=copies, launch=cfg)
-        ops.set_launch(wop, dt, "adjugate", "plain", keep)
+        if tune_launch:
+            # again with the launch the Wishart tuner picks on this image
+            wop = ops.wishart_launch_op(n)
+            keep = ops.get_launch(wop, dt, "adjugate", "plain")
+            cfg, _ = tune.tune_wishart(sets[0][0], sets[0][1], 8.0, reps=10)
+            ms = time_calls(call, steps_w, copies, torch)
+            res[f"wishart_2048_fwd_bwd_{tn}_autotuned"] = rate_row(n, ms, bpp, input_copies=copies, launch=cfg)
+            ops.set_launch(wop, dt, "adjugate", "plain", keep)
         del sets, ws
         torch.cuda.empty_cache()
     print(f"# wishart workload done", file=sys.stderr, flush=True)
+    return res
+
+
+def _batch_workload(torch, ops, dev, steps, tune_launch):
+    from paper_1807_08084_amd import synth, tune
+    from paper_1807_08084_amd.batch import BatchPlan
+    res = {}
     # batch: 64 images, FP32 compensated inverse + Wishart fwd + bwd, one graph
     # vs per-image loop; the graph again at the launch tune_batch picks
     imgs = synth.workload_batch()
@@ -409,24 +436,30 @@ def other_workloads(torch, ops, dev, steps):
     l_ms = time_calls(loop, steps, 3, torch)
     del outs, ws
     default_cfg = ops.get_launch(3, torch.float32, "adjugate", "compensated")
-    t_cfg, _ = tune.tune_batch(items, reps=5)
-    plan = BatchPlan(items, "adjugate", "compensated", status=False)
-    t_ms = time_calls(plan.run, steps, 3, torch)
-    plan.close()
-    ops.set_launch(3, torch.float32, "adjugate", "compensated", default_cfg)
-    res["batch_64_images"] = {"pixels": n, "graph_ms": round(g_ms, 4), "loop_ms": round(l_ms, 4),
-                              "graph_gpx_s": round(n / g_ms / 1e6, 3), "loop_gpx_s": round(n / l_ms / 1e6, 3),
-                              "graph_GB_s": round(148 * n / g_ms / 1e6, 1),
-                              "graph_frac_hbm": round(148 * n / g_ms / 1e6 / PEAK_HBM_GBS, 4),
-                              "launch": default_cfg,
-                              "autotuned_graph_ms": round(t_ms, 4), "autotuned_graph_gpx_s": round(n / t_ms / 1e6, 3),
-                              "autotuned_graph_frac_hbm": round(148 * n / t_ms / 1e6 / PEAK_HBM_GBS, 4),
-                              "autotuned_launch": t_cfg,
-                              "bytes_per_px": 148,
-                              "ops": "inverse+det of Z, Wishart fwd+bwd of S against Z (FP32 compensated)"}
+    rec = {"pixels": n, "graph_ms": round(g_ms, 4), "loop_ms": round(l_ms, 4),
+           "graph_gpx_s": round(n / g_ms / 1e6, 3), "loop_gpx_s": round(n / l_ms / 1e6, 3),
+           "graph_GB_s": round(148 * n / g_ms / 1e6, 1),
+           "graph_frac_hbm": round(148 * n / g_ms / 1e6 / PEAK_HBM_GBS, 4), "launch": default_cfg,
+           "bytes_per_px": 148, "ops": "inverse+det of Z, Wishart fwd+bwd of S against Z (FP32 compensated)"}
+    if tune_launch:
+        t_cfg, _ = tune.tune_batch(items, reps=5)
+        plan = BatchPlan(items, "adjugate", "compensated", status=False)
+        t_ms = time_calls(plan.run, steps, 3, torch)
+        plan.close()
+        ops.set_launch(3, torch.float32, "adjugate", "compensated", default_cfg)
+        rec.update({"autotuned_graph_ms": round(t_ms, 4), "autotuned_graph_gpx_s": round(n / t_ms / 1e6, 3),
+                    "autotuned_graph_frac_hbm": round(148 * n / t_ms / 1e6 / PEAK_HBM_GBS, 4),
+                    "autotuned_launch": t_cfg})
+    res["batch_64_images"] = rec
     del items
     torch.cuda.empty_cache()
     print(f"# batch workload done", file=sys.stderr, flush=True)
+    return res
+
+
+def _paper_workloads(torch, ops, dev):
+    from paper_1807_08084_amd import synth
+    res = {}
     # the paper's Table 2 shapes: 5,469,354 simulated M M^H matrices and a
     # 450 x 600 image, both forms, single launches like the paper's replicates
     shapes = (("simulated_5469354", synth.workload_paper_simulated()),
@@ -463,6 +496,10 @@ def main():
                     help="time the other workloads too (the default unless --no-rows or --no-workloads)")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the 2048^2 Wishart, 64-image batch and paper-shaped workloads")
+    ap.add_argument("--workload", action="append", choices=OTHER_WORKLOADS,
+                    help="time only these of the other workloads (repeatable; implies --workloads)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuned rows of the other workloads")
     ap.add_argument("--probe", action="store_true",
                     help="after the timed steps, run a one-plane copy of the same pixel count "
                          "(known bytes: calibrates the HBM traffic counters)")
@@ -574,8 +611,9 @@ def main():
         out["speedup_adjugate_vs_cholesky"]["scale_4096"] = equal_accuracy(srows)
         out["speedup_adjugate_vs_cholesky"]["paper_context"] = "about 2.2x on a GeForce 940M, OpenCL (Table 2)"
         out["copy_ceiling_frac_4096"] = round(srows["copy_9to10_f32"]["ms"] / srows["adjugate_compensated_f32"]["ms"], 4)
-    if args.workloads or not (args.no_rows or args.no_workloads):
-        out["workloads"] = other_workloads(torch, ops, dev, max(10, args.steps // 4))
+    if args.workload or args.workloads or not (args.no_rows or args.no_workloads):
+        out["workloads"] = other_workloads(torch, ops, dev, max(10, args.steps // 4),
+                                           tuple(args.workload or OTHER_WORKLOADS), not args.no_tune)
     del z32, outp, inv, det
     torch.cuda.empty_cache()
     if not args.no_cpu:

@@ -4,6 +4,8 @@
     python -m paper_1807_08084_amd.profile_summary traffic <fetch.db> <write.db> <out.txt> "<commands>" [n_px] [label]
     python -m paper_1807_08084_amd.profile_summary counters <pmc.db> <out.txt> "<command>"
     python -m paper_1807_08084_amd.profile_summary traffic_rows <fetch.db> <write.db> <out.txt> "<commands>"
+    python -m paper_1807_08084_amd.profile_summary traffic_kernel <fetch.db> <write.db> <out.txt> "<commands>" \
+        <kernel-prefix> <n_px> <alg_read_B_px> <alg_write_B_px> "<label>"
 
 ``trace`` lists each kernel's calls and mean duration (the --kernel-trace
 --stats view).  ``traffic`` turns per-dispatch FETCH_SIZE / WRITE_SIZE (KiB)
@@ -21,13 +23,26 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def source_hash() -> str:
+# the sources the per-call kernels (the inverse among them) are compiled from
+STEP_SOURCES = ("common.hpp", "pixel.hpp", "polsar.hip")
+
+
+def source_hash(names=STEP_SOURCES) -> str:
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(csrc, name), "rb").read())
+    for name in names:
+        h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()[:16]
+
+
+def all_sources_hash() -> str:
+    csrc = os.path.join(HERE, "csrc")
+    return source_hash(sorted(n for n in os.listdir(csrc) if n.endswith((".hip", ".hpp"))))
+
+
+def _hash_lines() -> str:
+    return (f"# source_hash = {source_hash()}  (common.hpp, pixel.hpp, polsar.hip)\n"
+            f"# all_sources_hash = {all_sources_hash()}  (every .hip and .hpp, the batch kernel's included)\n")
 
 
 def short(name: str) -> str:
@@ -39,7 +54,7 @@ def trace(db: str, out: str, command: str) -> None:
     rows = con.execute("select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
     with open(out, "w") as fh:
         fh.write(f"# rocprofv3 --kernel-trace --stats summary\n# command: {command}\n")
-        fh.write(f"# source_hash = {source_hash()}\n")
+        fh.write(_hash_lines())
         fh.write(f"{'kernel':60s} {'calls':>6s} {'total_us':>12s} {'avg_us':>10s} {'pct':>6s}\n")
         for name, calls, total, avg, pct in rows:
             fh.write(f"{short(name):60s} {calls:6d} {total:12.3f} {avg:10.3f} {pct:6.2f}\n")
@@ -92,6 +107,48 @@ def traffic(fetch_db: str, write_db: str, out: str, command: str, n_px: int = 40
     print(open(out).read())
 
 
+def traffic_kernel(fetch_db: str, write_db: str, out: str, command: str, prefix: str, n_px: int,
+                   alg_read: float, alg_write: float, label: str) -> None:
+    """HBM bytes per pixel of one kernel (the first whose name starts with
+    prefix; its dispatches at the most frequent grid size) over n_px pixels,
+    against its algorithmic bytes per pixel, FETCH_SIZE and WRITE_SIZE scaled
+    by the one-plane copy probe (4 bytes per pixel of the probe's grid)."""
+    f = _counter(fetch_db, "FETCH_SIZE", main_grid=True)
+    w = _counter(write_db, "WRITE_SIZE", main_grid=True)
+    fg = _counter_grid(fetch_db, "FETCH_SIZE")
+
+    def one_plane_copy(k):
+        args = k[k.find("<") + 1:k.rfind(">")].split(", ")
+        return k.startswith("k_copy<float,") and args[2:4] == ["1", "1"]
+    probe = next(k for k in f if one_plane_copy(k))
+    probe_px = fg[probe] * int(probe[probe.find("<") + 1:].split(", ")[1])  # threads x pixels per lane
+    kern = next(k for k in f if k.startswith(prefix))
+    f_scale = 4 * probe_px / (f[probe] * 1024)
+    w_scale = 4 * probe_px / (w[probe] * 1024)
+    rd = f[kern] * 1024 * f_scale / n_px
+    wr = w[kern] * 1024 * w_scale / n_px
+    with open(out, "w") as fh:
+        fh.write(f"# HBM traffic of {kern}, {label}\n# command: {command}\n")
+        fh.write(_hash_lines())
+        fh.write(f"# scales from the one-plane copy probe ({probe_px} pixels): FETCH_SIZE x{f_scale:.5f}, "
+                 f"WRITE_SIZE x{w_scale:.5f}\n")
+        fh.write(f"# kernel FETCH_SIZE {f[kern]:.1f} KiB, WRITE_SIZE {w[kern]:.1f} KiB per dispatch\n")
+        fh.write(f"read B/px {rd:.3f} (algorithmic {alg_read}, ratio {rd / alg_read:.5f})\n")
+        fh.write(f"write B/px {wr:.3f} (algorithmic {alg_write}, ratio {wr / alg_write:.5f})\n")
+    print(open(out).read())
+
+
+def _counter_grid(db: str, counter: str):
+    """Most frequent grid size (threads) of each kernel's dispatches."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select kernel_name, grid_size from counters_collection where counter_name=?",
+                       (counter,)).fetchall()
+    by = {}
+    for k, g in rows:
+        by.setdefault(short(k), []).append(g)
+    return {k: max(set(v), key=v.count) for k, v in by.items()}
+
+
 # Kernels of the bench rows on the 4096x4096 image and their algorithmic
 # bytes per pixel (read, written).
 ROW_KERNELS = [
@@ -122,7 +179,7 @@ def traffic_rows(fetch_db: str, write_db: str, out: str, command: str, n_px: int
     with open(out, "w") as fh:
         fh.write("# HBM traffic per pixel of the bench rows' kernels, 4096x4096 image\n")
         fh.write(f"# command: {command}\n")
-        fh.write(f"# source_hash = {source_hash()}\n")
+        fh.write(_hash_lines())
         fh.write(f"# scales from the one-plane copy probe: FETCH_SIZE x{f_scale:.5f}, WRITE_SIZE x{w_scale:.5f}\n")
         fh.write(f"{'kernel':36s} {'read B/px':>10s} {'alg':>5s} {'ratio':>7s} {'write B/px':>11s} {'alg':>5s} "
                  f"{'ratio':>7s}  what\n")
@@ -147,7 +204,7 @@ def counters(db: str, out: str, command: str, n_px: int = 4096 * 4096) -> None:
     names = sorted({cn for d in agg.values() for cn in d})
     with open(out, "w") as fh:
         fh.write(f"# rocprofv3 --pmc summary: mean per dispatch\n# command: {command}\n")
-        fh.write(f"# source_hash = {source_hash()}\n")
+        fh.write(_hash_lines())
         fh.write(f"# valu_per_px = SQ_INSTS_VALU * 64 / {n_px} (meaningful where the dispatch covers the image)\n")
         fh.write(f"{'kernel':44s} {'grid':>10s} {'calls':>5s} " + " ".join(f"{n:>15s}" for n in names)
                  + f" {'valu_per_px':>11s}\n")
@@ -166,6 +223,9 @@ if __name__ == "__main__":
         trace(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "counters":
         counters(sys.argv[2], sys.argv[3], sys.argv[4], *([int(sys.argv[5])] if len(sys.argv) > 5 else []))
+    elif sys.argv[1] == "traffic_kernel":
+        traffic_kernel(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6], int(sys.argv[7]),
+                       float(sys.argv[8]), float(sys.argv[9]), sys.argv[10])
     elif sys.argv[1] == "traffic_rows":
         traffic_rows(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
     else:
