@@ -221,7 +221,10 @@ def inverse_forms(torch, ops, dev, planes64: np.ndarray, steps: int, tag: str, t
         z = z32 if (dt == torch.float32 and z32 is not None) else ops.upload_planes(planes64, dt, dev)
         o = ops.empty_planes(10, n, dt, dev)
         for m, p in forms:
-            ms = time_calls(lambda m=m, p=p: ops.inv_det(z, m, p, inv=o[:9], det=o[9]), steps, 3, torch)
+            # each form warms for 0.1 s first: the power management settles
+            # on each kernel's own draw (the first calls after a switch or a
+            # fresh output buffer run up to 15% slow)
+            ms = time_calls(lambda m=m, p=p: ops.inv_det(z, m, p, inv=o[:9], det=o[9]), steps, 3, torch, 0.1)
             rows[f"{m}_{p}_{tn}"] = rate_row(n, ms, BYTES_PER_PX[tn],
                                              launch=ops.get_launch(ops.inv_det_launch_op(n), dt, m, p))
         if tune and dt == torch.float32:
@@ -229,7 +232,7 @@ def inverse_forms(torch, ops, dev, planes64: np.ndarray, steps: int, tag: str, t
             for m, p in TUNED_F32_FORMS:
                 keep = ops.get_launch(op, dt, m, p)
                 cfg, _ = ops.autotune_inv_det(z, m, p, reps=5)
-                ms = time_calls(lambda m=m, p=p: ops.inv_det(z, m, p, inv=o[:9], det=o[9]), steps, 3, torch)
+                ms = time_calls(lambda m=m, p=p: ops.inv_det(z, m, p, inv=o[:9], det=o[9]), steps, 3, torch, 0.1)
                 rows[f"{m}_{p}_{tn}_autotuned"] = rate_row(n, ms, BYTES_PER_PX[tn], launch=cfg)
                 ops.set_launch(op, dt, m, p, keep)
         del z, o
@@ -500,6 +503,8 @@ def main():
                     help="time only these of the other workloads (repeatable; implies --workloads)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuned rows of the other workloads")
+    ap.add_argument("--no-8192-rows", action="store_true",
+                    help="skip the rows of the two 8192^2 images (keep the 4096^2 rows; for profiling)")
     ap.add_argument("--probe", action="store_true",
                     help="after the timed steps, run a one-plane copy of the same pixel count "
                          "(known bytes: calibrates the HBM traffic counters)")
@@ -592,17 +597,19 @@ def main():
     }
     if not args.no_rows:
         ksteps = max(10, args.steps // 2)
-        # the other forms on the same image; the default step again
-        prec_rows = inverse_forms(torch, ops, dev, z64, ksteps, "precision 8192^2", tune=True, z32=z32)
-        out["precision_8192_rows"] = prec_rows
-        out["speedup_adjugate_vs_cholesky"] = {"precision_8192": equal_accuracy(prec_rows)}
-        img8 = synth.workload_scale8192()
-        s8 = img8.planes.reshape(9, -1)
-        del img8
-        rows8 = inverse_forms(torch, ops, dev, s8, ksteps, "scale 8192^2", tune=True)
-        del s8
-        out["scale_8192_rows"] = rows8
-        out["speedup_adjugate_vs_cholesky"]["scale_8192"] = equal_accuracy(rows8)
+        out["speedup_adjugate_vs_cholesky"] = {}
+        if not args.no_8192_rows:
+            # the other forms on the same image; the default step again
+            prec_rows = inverse_forms(torch, ops, dev, z64, ksteps, "precision 8192^2", tune=True, z32=z32)
+            out["precision_8192_rows"] = prec_rows
+            out["speedup_adjugate_vs_cholesky"]["precision_8192"] = equal_accuracy(prec_rows)
+            img8 = synth.workload_scale8192()
+            s8 = img8.planes.reshape(9, -1)
+            del img8
+            rows8 = inverse_forms(torch, ops, dev, s8, ksteps, "scale 8192^2", tune=True)
+            del s8
+            out["scale_8192_rows"] = rows8
+            out["speedup_adjugate_vs_cholesky"]["scale_8192"] = equal_accuracy(rows8)
         simg = synth.workload_scale(with_looks=True)
         srows = scale_rows(torch, ops, dev, simg, ksteps)
         del simg

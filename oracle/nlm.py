@@ -10,6 +10,14 @@ window offset the distance between every pixel and its neighbour:
 (the densities of the Introduction enter only through determinants and
 inverses), weights exp(-d/h) over the window clipped at the border, and the
 weighted mean of the neighbours' covariances.
+
+The two distances between complex Wishart laws of equal looks N are those
+of Frery, Nascimento and Cintra, "Analytic expressions for stochastic
+distances between relaxed complex Wishart distributions", IEEE Trans.
+Geosci. Remote Sens. 52(2), 2014.  The Bhattacharyya form follows from the
+Wishart density: the integral of sqrt(f_p f_q) is |A|^-N / (|Zp||Zq|)^(N/2)
+with A = (Zp^-1 + Zq^-1)/2, and |A| = |(Zp + Zq)/2| / (|Zp||Zq|) since
+Zp^-1 + Zq^-1 = Zp^-1 (Zp + Zq) Zq^-1.
 """
 from __future__ import annotations
 

@@ -5,17 +5,24 @@
 // the determinant (Bhattacharyya distance) of every covariance, and the
 // filtered covariance is the weighted mean
 //     out_p = sum_q w_pq Z_q / sum_q w_pq,   w_pq = exp(-d(Z_p, Z_q) / h).
-// Distances for N looks (the Sigma-free terms cancel):
+// Distances between complex Wishart laws of N looks (Frery, Nascimento and
+// Cintra, IEEE Trans. Geosci. Remote Sens. 52(2), 2014; the Sigma-free
+// terms cancel):
 //   KL: d = N/2 (tr(Z_p^-1 Z_q) + tr(Z_q^-1 Z_p)) - 3N
 //   B:  d = N (ln det((Z_p + Z_q)/2) - (ln det Z_p + ln det Z_q)/2)
 // with tr(AB) = a_A a_B + d_A d_B + f_A f_B + 2 (Re/Im products of b, c, e)
 // for Hermitian A, B, and det of the pair mean by the row-0 real-part
 // expansion (Eq. detr).  Windows are clipped at the image border.
 //
-// Blocks cover TW x TH output pixels.  For each window row offset dy the
-// block stages the band of TH rows x (TW + 2r) columns it needs (covariance
-// and inverse or log2 det, structure of arrays in LDS), then every lane
-// sweeps its 2r+1 horizontal neighbours in that band.
+// Blocks cover TW x TH output pixels.  For window row offset dy the block's
+// lanes need the band of TH input rows y0 + dy .. y0 + dy + TH - 1, each
+// TW + 2r columns wide (covariance and inverse or log2 det, structure of
+// arrays in LDS).  Consecutive bands share TH - 1 rows, so the band is a
+// ring of TH row slots: the first dy stages TH rows, every later dy stages
+// only its new bottom row into the slot of the row no lane needs any more,
+// and each input row is read from memory once per block (TH + 2r rows per
+// TH output rows).  Then every lane sweeps its 2r+1 horizontal neighbours
+// in its row of the band.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -84,38 +91,45 @@ __global__ __launch_bounds__(TW * TH) void k_nlm(NlmArgs a) {
   // w = exp2(alpha * s + beta): KL s = t1 + t2; B s = log2 det(Zp + Zq) - (lp + lq)/2
   const T alpha = DIST == 0 ? -N * log2e / (T(2) * (T)a.h) : -N / (T)a.h;
   const T beta = DIST == 0 ? T(3) * N * log2e / (T)a.h : T(3) * N / (T)a.h;
-  for (int dy = -r; dy <= r; ++dy) {
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < TH * bw; idx += TW * TH) {
-      const int row = idx / bw, col = idx % bw;
-      const int64_t gy = y0 + row + dy, gx = x0 - r + col;
-      if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
-        const int64_t i = gy * a.W + gx;
+  // input row j of the block (global row y0 - r + j) lives in ring slot j % TH
+  auto stage = [&](int j, int col) {
+    const int64_t gy = y0 - r + j, gx = x0 - r + col;
+    const int slot = j % TH;
+    if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
+      const int64_t i = gy * a.W + gx;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) band[k][row][col] = Z[k * a.zp + i];
-        if (DIST == 0) {
+      for (int k = 0; k < 9; ++k) band[k][slot][col] = Z[k * a.zp + i];
+      if (DIST == 0) {
 #pragma unroll
-          for (int k = 0; k < 9; ++k) band[9 + k][row][col] = A[k * a.ap + i];
-        } else {
-          band[9][row][col] = log2_(A[i]);
-        }
+        for (int k = 0; k < 9; ++k) band[9 + k][slot][col] = A[k * a.ap + i];
+      } else {
+        band[9][slot][col] = log2_(A[i]);
       }
+    }
+  };
+  for (int dy = -r; dy <= r; ++dy) {
+    __syncthreads();  // every lane is done with the slot about to be refilled
+    if (dy == -r) {
+      for (int idx = threadIdx.x; idx < TH * bw; idx += TW * TH) stage(idx / bw, idx % bw);  // the first band
+    } else {
+      for (int col = threadIdx.x; col < bw; col += TW * TH) stage(TH - 1 + dy + r, col);  // its new bottom row
     }
     __syncthreads();
     const int64_t qy = py + dy;
     if (!valid || qy < 0 || qy >= a.H) continue;
+    const int sl = (ty + dy + r) % TH;  // this lane's input row y0 + ty + dy
     const int lo = px >= r ? -r : (int)-px;
     const int hi = a.W - 1 - px >= r ? r : (int)(a.W - 1 - px);
     for (int dx = lo; dx <= hi; ++dx) {
       const int c = tx + dx + r;
       T q[9];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) q[k] = band[k][ty][c];
+      for (int k = 0; k < 9; ++k) q[k] = band[k][sl][c];
       T s;
       if (DIST == 0) {
         T t = T(0);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) t += ip2[k] * q[k] + band[9 + k][ty][c] * zp2[k];
+        for (int k = 0; k < 9; ++k) t += ip2[k] * q[k] + band[9 + k][sl][c] * zp2[k];
         s = t;
       } else {
         // det(Z_p + Z_q): the off-diagonal of zp2 is doubled, halve it back
@@ -124,7 +138,7 @@ __global__ __launch_bounds__(TW * TH) void k_nlm(NlmArgs a) {
         for (int k = 0; k < 9; ++k) m[k] = zp2[k] * (k < 3 ? T(1) : T(0.5)) + q[k];
         T cf[9];
         px::cofactors_plain(m, cf);
-        s = log2_(px::det_from_cofactors(m, cf)) - T(0.5) * (lp + band[9][ty][c]);
+        s = log2_(px::det_from_cofactors(m, cf)) - T(0.5) * (lp + band[9][sl][c]);
       }
       const T w = exp2_(alpha * s + beta);
 #pragma unroll

@@ -149,21 +149,25 @@ struct MultilookArgs {
   const void* looks;
   int64_t lp;
   int n_looks;
+  double inv_n;  // 1 / n_looks (FP64)
   void* z;  // optional output of the multilook covariance
   int64_t zp;
   InvDetArgs o;  // outputs (o.z unused), n, nvec, tiles
 };
 
 // Fused multilook front end + inverse/determinant: per lane V pixels, the N
-// looks are streamed (6 planes each) into FP64 accumulators, Z is rounded to
-// the storage type, optionally stored, and inverted exactly as k_inv_det
-// inverts a stored Z.
+// looks are streamed (6 planes each) into FP64 accumulators, scaled by 1/N
+// (one FP64 multiply per component: exact for N a power of two, else within
+// an FP64 rounding of the quotient, far below the storage rounding), Z is
+// rounded to the storage type, optionally stored, and inverted exactly as
+// k_inv_det inverts a stored Z (the FP32 compensated form through the
+// wave's FP64 queue).
 template <class T, int OP, int V, bool NT>
 __global__ __launch_bounds__(256) void k_multilook(MultilookArgs a) {
   const T* __restrict__ S = (const T*)a.looks;
   const int B = blockDim.x;
   unsigned c0 = 0, c1 = 0, c2 = 0;
-  const double inv_n_den = (double)a.n_looks;
+  const double inv_n = a.inv_n;
   for (int64_t tile = blockIdx.x; tile < a.o.tiles; tile += gridDim.x) {
     const int64_t v = tile * (int64_t)B + threadIdx.x;
     if (v < a.o.nvec) {
@@ -187,12 +191,32 @@ __global__ __launch_bounds__(256) void k_multilook(MultilookArgs a) {
 #pragma unroll
       for (int l = 0; l < V; ++l)
 #pragma unroll
-        for (int k = 0; k < 9; ++k) zz[k][l] = (T)(acc[l][k] / inv_n_den);
+        for (int k = 0; k < 9; ++k) zz[k][l] = (T)(acc[l][k] * inv_n);
       if (a.z) {
 #pragma unroll
         for (int k = 0; k < 9; ++k) store_v<T, V, NT>((T*)a.z + k * a.zp + v * V, zz[k]);
       }
-      inv_det_vec<T, OP, V, NT>(a.o, zz, v, c0, c1, c2);
+      if constexpr (OP == ADJ_COMP && std::is_same<T, float>::value) {
+        extern __shared__ __align__(16) float polsar_dyn_lds[];
+        const int w = threadIdx.x >> 6, nw = B >> 6;
+        float* q = polsar_dyn_lds + (size_t)w * 64 * V * QUEUE_WORDS;
+        uint8_t* qs = (uint8_t*)(polsar_dyn_lds + (size_t)nw * 64 * V * QUEUE_WORDS) + w * 64 * V;
+        const bool valid[1] = {true};
+        auto load = [&](int, float (&in)[9][V]) {
+#pragma unroll
+          for (int k = 0; k < 9; ++k)
+#pragma unroll
+            for (int l = 0; l < V; ++l) in[k][l] = zz[k][l];
+        };
+        float out[1][9][V], dt[1][V];
+        int st[1][V];
+        comp_f32_wave<1, V>(load, valid, out, dt, st, q, qs);
+#pragma unroll
+        for (int l = 0; l < V; ++l) tally(st[0][l], c0, c1, c2);
+        store_vec<T, V, NT>(a.o, out[0], dt[0], st[0], v);
+      } else {
+        inv_det_vec<T, OP, V, NT>(a.o, zz, v, c0, c1, c2);
+      }
     }
     if (V > 1 && tile == a.o.tiles - 1) {
       const int64_t i = a.o.nvec * V + threadIdx.x;
@@ -206,7 +230,7 @@ __global__ __launch_bounds__(256) void k_multilook(MultilookArgs a) {
         }
         T zz[9], xx[9], dt;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) zz[k] = (T)(acc[k] / inv_n_den);
+        for (int k = 0; k < 9; ++k) zz[k] = (T)(acc[k] * inv_n);
         if (a.z)
 #pragma unroll
           for (int k = 0; k < 9; ++k) ((T*)a.z)[k * a.zp + i] = zz[k];
@@ -592,8 +616,8 @@ polsar_launch default_launch(int op, int dtype, int method, int prec) {
       return f64 ? polsar_launch{128, 1, 0, 1, 8, 4} : polsar_launch{128, 1, 0, 1, 8, 5};
     case 2:
       return f64 ? polsar_launch{256, 1, 0, 1, 8, 4} : polsar_launch{128, 1, 0, 1, 16, 0};
-    case 3:
-      return f64 ? polsar_launch{256, 1, 2, 1, 16, 6} : polsar_launch{256, 1, 16, 1, 16, 0};
+    case 3:  // FP32: 2 blocks per CU, the tuner's pick on the 64-image batch (36 Gpx/s, 16 per CU: 33)
+      return f64 ? polsar_launch{256, 1, 2, 1, 16, 6} : polsar_launch{256, 1, 2, 1, 16, 0};
     case 4:  // copy probe: few waves in flight stream best
       return polsar_launch{64, 1, 0, 1, 16, 5};
     case 6:  // the inverse kernel on images of at least INV_DET_LARGE pixels
@@ -842,7 +866,8 @@ hipError_t dispatch_multilook_v(const polsar_launch& c, MultilookArgs& a, hipStr
   a.o.nvec = a.o.n / V;
   a.o.tiles = std::max<int64_t>(1, (a.o.nvec + c.block - 1) / c.block);
   const int64_t grid = launch_grid(c, a.o.tiles, a.o.counters != nullptr);
-  const size_t lds = launch_lds(c, 0);
+  const size_t lds =
+      launch_lds(c, (OP == ADJ_COMP && std::is_same<T, float>::value) ? comp_queue_bytes(c.block, V) : 0);
   if (c.nontemporal)
     hipLaunchKernelGGL((k_multilook<T, OP, V, true>), dim3((unsigned)grid), dim3(c.block), lds, s, a);
   else
@@ -1087,7 +1112,8 @@ int polsar_multilook_inv_det(int dtype, int method, int precision, int64_t n, in
         if (all[p].hi > all[p].lo && all[q].hi > all[q].lo && overlap(all[p], all[q])) return POLSAR_E_ALIAS;
   }
   if (n == 0) return POLSAR_OK;
-  MultilookArgs a{looks, looks_pitch, n_looks, z, z_pitch, InvDetArgs{nullptr, 0, inv, inv_pitch, det, status, counters, n, 0, 0}};
+  MultilookArgs a{looks, looks_pitch, n_looks, 1.0 / n_looks, z, z_pitch,
+                  InvDetArgs{nullptr, 0, inv, inv_pitch, det, status, counters, n, 0, 0}};
   const bool vec = vec_ok(looks, looks_pitch, es) && vec_ok(z, z_pitch, es) && vec_ok(inv, inv_pitch, es) && vec_ok(det, 0, es) &&
         (status == nullptr || ((uintptr_t)status % (16 / es)) == 0);
   const polsar_launch c = get_cfg(2, dtype, method, precision);
