@@ -209,6 +209,28 @@ F64_FORMS = [("adjugate", "compensated"), ("adjugate", "plain"), ("cholesky", "p
 TUNED_F32_FORMS = [("adjugate", "compensated"), ("cholesky", "compensated"), ("cholesky", "wide")]
 
 
+COPY_SHAPES = ((64, 16, 5), (64, 16, 4), (64, 16, 6), (64, 8, 8), (128, 16, 3), (128, 8, 0), (128, 8, 6),
+               (256, 16, 2), (256, 8, 0), (256, 16, 0))
+
+
+def copy_ceiling(torch, ops, src, dst, n_in: int, n_out: int, n: int, steps: int):
+    """Best time of the plane-copy probe (n_in planes in, n_out out, no
+    arithmetic) over a sweep of launch shapes (block, access width,
+    resident-block cap): the practical streaming ceiling of that mix of
+    plane streams.  Returns (ms, launch)."""
+    dt = src.dtype
+    keep = ops.get_launch(4, dt, "adjugate", "plain")
+    best = None
+    for cb, cvb, cbpc in COPY_SHAPES:
+        cfg = dict(block=cb, unroll=1, grid_per_cu=0, nontemporal=1, vector_bytes=cvb, blocks_per_cu=cbpc)
+        ops.set_launch(4, dt, "adjugate", "plain", cfg)
+        ms = time_calls(lambda: ops.stream_copy(src, dst, n_in, n_out, n), steps, 2, torch)
+        if best is None or ms < best[0]:
+            best = (ms, cfg)
+    ops.set_launch(4, dt, "adjugate", "plain", keep)
+    return best
+
+
 def inverse_forms(torch, ops, dev, planes64: np.ndarray, steps: int, tag: str, tune: bool,
                   z32=None) -> dict:
     """Every inverse form on one image, FP32 and FP64, at the library's default
@@ -274,21 +296,17 @@ def scale_rows(torch, ops, dev, img, steps: int) -> dict:
     for dt, tname in ((torch.float32, "f32"), (torch.float64, "f64")):
         zt = ops.upload_planes(z64, dt, dev)
         # measured ceiling: the same 9-in / 10-out plane streams with no
-        # arithmetic, best of a sweep of launch shapes (block, access width,
-        # resident-block cap)
+        # arithmetic, best of a sweep of launch shapes
         dst = ops.empty_planes(10, n_px, dt, dev)
-        keep_copy = ops.get_launch(4, dt, "adjugate", "plain")
-        best = None
-        for cb, cvb, cbpc in ((64, 16, 5), (64, 16, 4), (64, 16, 6), (64, 8, 8), (128, 16, 3), (128, 8, 0),
-                              (128, 8, 6), (256, 16, 2), (256, 8, 0), (256, 16, 0)):
-            ccfg = dict(block=cb, unroll=1, grid_per_cu=0, nontemporal=1, vector_bytes=cvb, blocks_per_cu=cbpc)
-            ops.set_launch(4, dt, "adjugate", "plain", ccfg)
-            c_ms = time_calls(lambda: ops.stream_copy(zt, dst, 9, 10, n_px), steps, 2, torch)
-            if best is None or c_ms < best[0]:
-                best = (c_ms, ccfg)
-        ops.set_launch(4, dt, "adjugate", "plain", keep_copy)
-        rows[f"copy_9to10_{tname}"] = rate_row(n_px, best[0], BYTES_PER_PX[tname], launch=best[1])
+        c_ms, ccfg = copy_ceiling(torch, ops, zt, dst, 9, 10, n_px, steps)
+        rows[f"copy_9to10_{tname}"] = rate_row(n_px, c_ms, BYTES_PER_PX[tname], launch=ccfg)
         del dst
+        # and the Wishart kernel's mix, 18 planes in and 9 out
+        src18 = ops.empty_planes(18, n_px, dt, dev)
+        dst9 = ops.empty_planes(9, n_px, dt, dev)
+        c_ms, ccfg = copy_ceiling(torch, ops, src18, dst9, 18, 9, n_px, steps)
+        rows[f"copy_18to9_{tname}"] = rate_row(n_px, c_ms, WISHART_BYTES_PER_PX[tname], launch=ccfg)
+        del src18, dst9
         # Wishart forward+backward (fused): S = Z + 0.1 tr(Z)/3 I against Z
         sig = ops.empty_planes(9, n_px, dt, dev)
         sig.copy_(zt)
@@ -297,7 +315,7 @@ def scale_rows(torch, ops, dev, img, steps: int) -> dict:
             sig[k] += tr
         ws = torch.empty(max(1, ops.workspace_bytes(dt, n_px) // 8 + 1), dtype=torch.float64, device=dev)
         w_ms = time_calls(lambda: ops.wishart_loglik(sig, zt, 4.0, forward=True, backward=True, workspace=ws),
-                          steps, 3, torch)
+                          steps, 3, torch, 0.1)
         rows[f"wishart_fwd_bwd_{tname}"] = rate_row(n_px, w_ms, WISHART_BYTES_PER_PX[tname])
         del sig, ws, zt
         torch.cuda.empty_cache()
@@ -305,16 +323,21 @@ def scale_rows(torch, ops, dev, img, steps: int) -> dict:
     lk = ops.upload_planes(img.looks.reshape(24, -1).astype(np.float32), torch.float32, dev)
     for want_z, tag in ((False, "multilook_fused_f32"), (True, "multilook_fused_with_z_f32")):
         m_ms = time_calls(lambda: ops.multilook_inv_det(lk, 4, "adjugate", "compensated", want_z=want_z),
-                          steps, 3, torch)
+                          steps, 3, torch, 0.1)
         mb = 24 * 4 + 40 + (36 if want_z else 0)
         rows[tag] = rate_row(n_px, m_ms, mb, bytes_per_px=mb)
+    # the multilook's mix without arithmetic: 24 planes in, 10 out
+    dst10 = ops.empty_planes(10, n_px, torch.float32, dev)
+    c_ms, ccfg = copy_ceiling(torch, ops, lk, dst10, 24, 10, n_px, steps)
+    rows["copy_24to10_f32"] = rate_row(n_px, c_ms, 136, launch=ccfg)
+    del dst10
     del lk
     torch.cuda.empty_cache()
     # spatial (boxcar) multilook of a single-look image, 3x3 and 7x7 windows,
     # inverse + det out; 24 B in + 40 B out per px
     sl = ops.upload_planes(synth.workload_boxcar().astype(np.float32).reshape(6, 4096, 4096), torch.float32, dev)
     for r in (1, 3):
-        b_ms = time_calls(lambda: ops.boxcar_inv_det(sl, r, "adjugate", "compensated"), steps, 3, torch)
+        b_ms = time_calls(lambda: ops.boxcar_inv_det(sl, r, "adjugate", "compensated"), steps, 3, torch, 0.1)
         rows[f"boxcar_r{r}_f32"] = rate_row(n_px, b_ms, 64, bytes_per_px=64, window=f"{2 * r + 1}x{2 * r + 1}")
     del sl
     torch.cuda.empty_cache()
@@ -438,11 +461,21 @@ def _batch_workload(torch, ops, dev, steps, tune_launch):
             ops.wishart_loglik(it["sigma"], it["z"], it["n_looks"], forward=True, backward=True, workspace=ws)
     l_ms = time_calls(loop, steps, 3, torch)
     del outs, ws
+    # the batch's mix without arithmetic: Z and S in (18 planes), inverse, det
+    # and gradient out (19), over as many pixels as the 64 images hold
+    src18 = ops.empty_planes(18, n, torch.float32, dev)
+    dst19 = ops.empty_planes(19, n, torch.float32, dev)
+    c_ms, c_cfg = copy_ceiling(torch, ops, src18, dst19, 18, 19, n, steps)
+    del src18, dst19
+    torch.cuda.empty_cache()
     default_cfg = ops.get_launch(3, torch.float32, "adjugate", "compensated")
     rec = {"pixels": n, "graph_ms": round(g_ms, 4), "loop_ms": round(l_ms, 4),
            "graph_gpx_s": round(n / g_ms / 1e6, 3), "loop_gpx_s": round(n / l_ms / 1e6, 3),
            "graph_GB_s": round(148 * n / g_ms / 1e6, 1),
            "graph_frac_hbm": round(148 * n / g_ms / 1e6 / PEAK_HBM_GBS, 4), "launch": default_cfg,
+           "copy_18to19_GB_s": round(148 * n / c_ms / 1e6, 1),
+           "copy_18to19_frac_hbm": round(148 * n / c_ms / 1e6 / PEAK_HBM_GBS, 4),
+           "graph_frac_of_copy_ceiling": round(c_ms / g_ms, 4), "copy_launch": c_cfg,
            "bytes_per_px": 148, "ops": "inverse+det of Z, Wishart fwd+bwd of S against Z (FP32 compensated)"}
     if tune_launch:
         t_cfg, _ = tune.tune_batch(items, reps=5)

@@ -191,7 +191,13 @@ typedef enum { POLSAR_FWD = 1, POLSAR_BWD = 2, POLSAR_FWD_BWD = 3 } polsar_pass;
  *              partial sums, which a second kernel adds in tile order
  *              (deterministic).  Calls that share a workspace must not
  *              overlap in time (one stream, or synchronised streams).
- *   counters   as for polsar_inv_det ([not_pd, 0, nonfinite] for S).
+ *   counters   as for polsar_inv_det: [not_pd, low_accuracy, nonfinite] for
+ *              S, where low_accuracy counts the positive-definite pixels
+ *              whose determinant of S may be off by more than 1e-3 relative
+ *              (an a-priori bound of the plain evaluation in the storage
+ *              type, gamma_8 sum |x_i| (|c_i| + sum of c_i's product
+ *              magnitudes)): their terms and gradient carry errors of that
+ *              order or more (ill-conditioned S in FP32).
  * Launch shape: op 1 of polsar_get_launch, op 5 below 2^23 pixels (see
  * polsar_wishart_launch_op); the loss's summation order follows the tiles,
  * so it can differ between the two in the last bits. */
@@ -326,9 +332,14 @@ int polsar_autotune_inv_det(int dtype, int method, int precision, int64_t n,
                             void* stream);
 
 /* Bandwidth probe: copies n_in planes of n elements (pitch src_pitch) to
- * n_out planes (pitch dst_pitch; plane k of dst takes plane k mod n_in) with
- * the same access pattern as the inverse kernels, for a measured ceiling.
- * (n_in, n_out) is (9, 10), (18, 9) or (1, 1); planes 16-byte aligned.
+ * n_out planes (pitch dst_pitch; plane k of dst takes plane k mod n_in, or,
+ * with fewer outputs than inputs, the sum of the input planes j with
+ * j mod n_out == k, so that every input is read) with
+ * the same access pattern as the inverse kernels, for a measured ceiling of
+ * each kernel's mix of plane streams: (n_in, n_out) is (9, 10) (inverse),
+ * (18, 9) (Wishart forward+backward), (18, 19) (the batch: inverse and
+ * Wishart), (24, 10) (four-look multilook) or (1, 1) (counter calibration);
+ * planes 16-byte aligned.
  * Launch shape: op 4 of polsar_get_launch. */
 int polsar_stream_copy(int dtype, int64_t n, const void* src, int64_t src_pitch, int n_in,
                        void* dst, int64_t dst_pitch, int n_out, void* stream);

@@ -580,14 +580,50 @@ PX_HD T herm_w_diag(const T* P, const Cx<T> (&W)[3][3]) {
   return q;
 }
 
+// A-priori bound on the rounding error of the plain determinant of
+// Eq. (detr) with the cofactors of Eq. (adjoint_elements): each cofactor
+// component is a sum of three products, evaluated with at most three
+// roundings (fused or not), so |c^_i - c_i| <= gamma_3 S_i with S_i the sum
+// of its products' magnitudes; the five-term sum of x_i c^_i adds at most
+// gamma_5 sum |x_i c^_i|.  Together, with gamma_n = n u / (1 - n u):
+//   |det^ - det| <= gamma_8 sum_i |x_i| (|c^_i| + S_i),
+// x = (a, Re b, Im b, Re c, Im c) and i over a_c, Re b_c, Im b_c, Re c_c,
+// Im c_c; plus 64 eta (1 + sum |x_i|) for operations whose results are
+// subnormal (eta the smallest normal number), as in det_comp.  Evaluated in
+// the storage type, rounding up by (1 + 16u).
+template <class T>
+PX_HD T det_plain_bound(const T z[9], const T c[9]) {
+  const T a = z[0], d = z[1], f = z[2], br = z[3], bi = z[4], cr = z[5], ci = z[6], er = z[7], ei = z[8];
+  const T s0 = abs_(d * f) + (er * er + ei * ei);
+  const T s3 = abs_(cr * er) + abs_(ci * ei) + abs_(br * f);
+  const T s4 = abs_(ci * er) + abs_(cr * ei) + abs_(bi * f);
+  const T s5 = abs_(br * er) + abs_(bi * ei) + abs_(cr * d);
+  const T s6 = abs_(br * ei) + abs_(bi * er) + abs_(ci * d);
+  const T sum = abs_(a) * (abs_(c[0]) + s0) + abs_(br) * (abs_(c[3]) + s3) + abs_(bi) * (abs_(c[4]) + s4) +
+                abs_(cr) * (abs_(c[5]) + s5) + abs_(ci) * (abs_(c[6]) + s6);
+  constexpr double u = Eps<T>::u;
+  constexpr T g8 = (T)(8.0 * u / (1.0 - 8.0 * u) * (1.0 + 16.0 * u));
+  constexpr T eta64 = (T)(64.0 * Eps<T>::eta);
+  return fma_(g8, sum, eta64 * (T(1) + abs_(a) + abs_(br) + abs_(bi) + abs_(cr) + abs_(ci)));
+}
+
+// Relative determinant error bound of S above which a Wishart term is
+// counted as of low accuracy.
+constexpr double WISHART_LOW_REL = 1e-3;
+
+// The Wishart term of one pixel and/or its packed gradient.  low (optional)
+// is set when S is positive definite but its determinant may be off by more
+// than WISHART_LOW_REL relative (det_plain_bound): the term and the gradient
+// of such a pixel carry errors of that order or more.
 template <class T>
 PX_HD int wishart_pixel(const T s[9], const T z[9], T n_looks, bool want_ell, T& ell, bool want_grad, T grad[9],
-                        T gscale) {
+                        T gscale, bool* low = nullptr) {
   T c[9];
   cofactors_plain(s, c);
   const T det = det_from_cofactors(s, c);
   const T t = T(1) / det;
   const int st = classify(det, t, s[0], c[2]);
+  if (low) *low = st == ST_OK && det_plain_bound(s, c) > (T)WISHART_LOW_REL * det;
   if (want_ell) {
     const T tr = c[0] * z[0] + c[1] * z[1] + c[2] * z[2] +
                  T(2) * (c[3] * z[3] + c[4] * z[4] + c[5] * z[5] + c[6] * z[6] + c[7] * z[7] + c[8] * z[8]);

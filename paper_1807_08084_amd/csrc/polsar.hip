@@ -471,17 +471,19 @@ struct WishartArgs {
 
 template <class T, int V, bool NT>
 __device__ __forceinline__ double wishart_vec(const WishartArgs& a, const T (&s)[9][V], const T (&z)[9][V],
-                                              int64_t v, T gscale, unsigned& c0, unsigned& c2) {
+                                              int64_t v, T gscale, unsigned& c0, unsigned& c1, unsigned& c2) {
   T ell[V], g[9][V];
   double acc = 0.0;
-  unsigned dummy = 0;
 #pragma unroll
   for (int l = 0; l < V; ++l) {
     T ss[9], zz[9], gg[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) { ss[k] = s[k][l]; zz[k] = z[k][l]; }
-    const int st = px::wishart_pixel<T>(ss, zz, (T)a.n_looks, a.fwd, ell[l], a.bwd, gg, gscale);
-    tally(st, c0, dummy, c2);
+    bool low = false;
+    const int st = px::wishart_pixel<T>(ss, zz, (T)a.n_looks, a.fwd, ell[l], a.bwd, gg, gscale,
+                                        a.counters ? &low : nullptr);
+    tally(st, c0, c1, c2);
+    c1 += low;
     if (a.fwd) acc += (double)ell[l];
     if (a.bwd)
 #pragma unroll
@@ -503,7 +505,7 @@ __global__ __launch_bounds__(256) void k_wishart(WishartArgs a) {
   const T* __restrict__ Z = (const T*)a.z;
   const int B = blockDim.x;
   const T gscale = a.bwd ? (a.grad_loss ? (T)*a.grad_loss : T(1)) : T(1);
-  unsigned c0 = 0, c2 = 0;
+  unsigned c0 = 0, c1 = 0, c2 = 0;
   for (int64_t tile = blockIdx.x; tile < a.tiles; tile += gridDim.x) {
     const int64_t v0 = tile * (int64_t)(B * U) + threadIdx.x;
     T s[U][9][V], z[U][9][V];
@@ -521,7 +523,7 @@ __global__ __launch_bounds__(256) void k_wishart(WishartArgs a) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t v = v0 + (int64_t)u * B;
-      if (v < a.nvec) acc += wishart_vec<T, V, NT>(a, s[u], z[u], v, gscale, c0, c2);
+      if (v < a.nvec) acc += wishart_vec<T, V, NT>(a, s[u], z[u], v, gscale, c0, c1, c2);
     }
     if (V > 1 && tile == a.tiles - 1) {
       const int64_t i = a.nvec * V + threadIdx.x;
@@ -529,9 +531,11 @@ __global__ __launch_bounds__(256) void k_wishart(WishartArgs a) {
         T ss[9], zz[9], gg[9], el;
 #pragma unroll
         for (int k = 0; k < 9; ++k) { ss[k] = S[k * a.sp + i]; zz[k] = Z[k * a.zp + i]; }
-        unsigned dummy = 0;
-        const int st = px::wishart_pixel<T>(ss, zz, (T)a.n_looks, a.fwd, el, a.bwd, gg, gscale);
-        tally(st, c0, dummy, c2);
+        bool low = false;
+        const int st = px::wishart_pixel<T>(ss, zz, (T)a.n_looks, a.fwd, el, a.bwd, gg, gscale,
+                                            a.counters ? &low : nullptr);
+        tally(st, c0, c1, c2);
+        c1 += low;
         if (a.fwd) {
           acc += (double)el;
           if (a.ell) ((T*)a.ell)[i] = el;
@@ -546,7 +550,7 @@ __global__ __launch_bounds__(256) void k_wishart(WishartArgs a) {
       if (threadIdx.x == 0) a.partial[tile] = bs;
     }
   }
-  if (a.counters) flush_counters(a.counters, c0, 0u, c2);
+  if (a.counters) flush_counters(a.counters, c0, c1, c2);
 }
 
 // Fixed-order sum of `count` partials into *out (one block of REDUCE_BLOCK
@@ -559,6 +563,10 @@ __global__ __launch_bounds__(REDUCE_BLOCK) void k_reduce(const double* __restric
 }
 
 // ------------------------------------------------------------------ copy probe
+// Output plane k is input plane k mod NI when there are at least as many
+// outputs as inputs; with fewer outputs it is the sum of the inputs j with
+// j mod NO == k, so that every input plane is read (a plane no output used
+// would not be loaded at all).
 template <class T, int V, int NI, int NO, bool NT>
 __global__ __launch_bounds__(256) void k_copy(const T* __restrict__ src, int64_t sp, T* __restrict__ dst,
                                               int64_t dp, int64_t nvec, int64_t n) {
@@ -567,13 +575,23 @@ __global__ __launch_bounds__(256) void k_copy(const T* __restrict__ src, int64_t
     T in[NI][V];
 #pragma unroll
     for (int k = 0; k < NI; ++k) load_v<T, V, NT>(src + k * sp + v * V, in[k]);
+    if constexpr (NI > NO) {
+#pragma unroll
+      for (int j = NO; j < NI; ++j)
+#pragma unroll
+        for (int l = 0; l < V; ++l) in[j % NO][l] += in[j][l];
+    }
 #pragma unroll
     for (int k = 0; k < NO; ++k) store_v<T, V, NT>(dst + k * dp + v * V, in[k % NI]);
   }
   if (blockIdx.x == 0) {
     const int64_t i = nvec * V + threadIdx.x;
     if (i < n)
-      for (int k = 0; k < NO; ++k) dst[k * dp + i] = src[(k % NI) * sp + i];
+      for (int k = 0; k < NO; ++k) {
+        T x = src[(k % NI) * sp + i];
+        for (int j = k + NO; j < NI; j += NO) x += src[j * sp + i];
+        dst[k * dp + i] = x;
+      }
   }
 }
 
@@ -614,7 +632,9 @@ polsar_launch default_launch(int op, int dtype, int method, int prec) {
       return f64 ? polsar_launch{128, 1, 0, 1, 8, 4} : polsar_launch{256, 1, 0, 1, 16, 0};
     case 5:  // the Wishart kernel below WISHART_SMALL pixels: more, smaller tiles
       return f64 ? polsar_launch{128, 1, 0, 1, 8, 4} : polsar_launch{128, 1, 0, 1, 8, 5};
-    case 2:
+    case 2:  // FP32 compensated: 8-byte accesses, at most 8 blocks of 256 lanes per CU (0.75 of HBM on the
+             // four-look 4096x4096 image against 0.67 with 16-byte accesses and no cap)
+      if (!f64 && !chol && prec == POLSAR_COMPENSATED) return polsar_launch{256, 1, 0, 1, 8, 8};
       return f64 ? polsar_launch{256, 1, 0, 1, 8, 4} : polsar_launch{128, 1, 0, 1, 16, 0};
     case 3:  // FP32: 2 blocks per CU, the tuner's pick on the 64-image batch (36 Gpx/s, 16 per CU: 33)
       return f64 ? polsar_launch{256, 1, 2, 1, 16, 6} : polsar_launch{256, 1, 2, 1, 16, 0};
@@ -1362,7 +1382,8 @@ int polsar_stream_copy(int dtype, int64_t n, const void* src, int64_t src_pitch,
   int r = check_planes(src, src_pitch, n, es);
   if (r) return r;
   if ((r = check_planes(dst, dst_pitch, n, es))) return r;
-  const bool shape_ok = (n_in == 9 && n_out == 10) || (n_in == 18 && n_out == 9) || (n_in == 1 && n_out == 1);
+  const bool shape_ok = (n_in == 9 && n_out == 10) || (n_in == 18 && n_out == 9) || (n_in == 18 && n_out == 19) ||
+                        (n_in == 24 && n_out == 10) || (n_in == 1 && n_out == 1);
   if (!shape_ok) return POLSAR_E_UNSUPPORTED;
   if (!vec_ok(src, src_pitch, es) || !vec_ok(dst, dst_pitch, es)) return POLSAR_E_ALIGN;
   if (n > 0 && overlap(span(src, n_in, src_pitch, n, es), span(dst, n_out, dst_pitch, n, es))) return POLSAR_E_ALIAS;
@@ -1387,7 +1408,9 @@ int polsar_stream_copy(int dtype, int64_t n, const void* src, int64_t src_pitch,
 #define POLSAR_COPY_V(T, V)                                                                                    \
   do {                                                                                                        \
     if (n_in == 9) POLSAR_COPY(T, V, 9, 10);                                                                  \
-    else if (n_in == 18) POLSAR_COPY(T, V, 18, 9);                                                            \
+    else if (n_in == 18 && n_out == 9) POLSAR_COPY(T, V, 18, 9);                                              \
+    else if (n_in == 18) POLSAR_COPY(T, V, 18, 19);                                                           \
+    else if (n_in == 24) POLSAR_COPY(T, V, 24, 10);                                                           \
     else POLSAR_COPY(T, V, 1, 1);                                                                             \
   } while (0)
   if (dtype == POLSAR_F32) {

@@ -26,6 +26,8 @@ def lib():
         L.host_adjugate_comp_f32.restype = i64
         L.host_adjugate_comp_f64.argtypes = [i64, vp, i64, vp, vp, vp, ctypes.c_int]
         L.host_adjugate_comp_f64.restype = i64
+        L.host_det_plain_bound_f32.argtypes = [i64, vp, i64, vp, vp, ctypes.c_int]
+        L.host_det_plain_bound_f32.restype = None
         _L = L
     return _L
 
@@ -53,3 +55,12 @@ def adjugate_comp_f64(z):
     inv, det, st = np.empty((9, n)), np.empty(n), np.empty(n, np.uint8)
     lib().host_adjugate_comp_f64(n, _p(z), n, _p(inv), _p(det), _p(st), _threads())
     return inv, det, st
+
+
+def det_plain_bound_f32(z):
+    """Plain FP32 determinant and its a-priori error bound (host build)."""
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.float32).reshape(9, -1))
+    n = z.shape[1]
+    det, bound = np.empty(n, np.float32), np.empty(n, np.float32)
+    lib().host_det_plain_bound_f32(n, _p(z), n, _p(det), _p(bound), _threads())
+    return det, bound

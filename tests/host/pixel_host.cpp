@@ -43,4 +43,17 @@ int64_t host_adjugate_comp_f64(int64_t n, const double* z, int64_t zp, double* i
   return bad;
 }
 
+// Plain determinant (Eq. detr with the plain cofactors) and its a-priori
+// rounding bound, as the Wishart term evaluates them.
+void host_det_plain_bound_f32(int64_t n, const float* z, int64_t zp, float* det, float* bound, int threads) {
+#pragma omp parallel for num_threads(threads) schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    float zz[9], c[9];
+    for (int k = 0; k < 9; ++k) zz[k] = z[k * zp + i];
+    px::cofactors_plain(zz, c);
+    det[i] = px::det_from_cofactors(zz, c);
+    bound[i] = px::det_plain_bound(zz, c);
+  }
+}
+
 }  // extern "C"

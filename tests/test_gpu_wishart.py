@@ -192,3 +192,42 @@ def test_both_launch_entries_at_the_size_boundary(ops, width):
     d = (to_np(g).reshape(9, -1)[:, idx] - gh) - gl
     err = np.linalg.norm(d, axis=0) / np.linalg.norm(gh, axis=0)
     assert np.all(err <= 2e-6 * ks * ks), err.max()
+
+
+@pytest.mark.parametrize("launch_n", [40000, 70000])
+def test_low_accuracy_count(ops, case, launch_n):
+    """counters[1] counts the positive-definite S whose plain determinant may
+    be off by more than 1e-3 relative (the a-priori bound, pinned on the host
+    against the __float128 oracle in test_host_pixel.py).  The Wishart image's
+    well-conditioned S (kappa <= ~30) counts none; Haar-rotated FP32 S with
+    eigenvalues (1, l2, 10^-U(0, 6)) count exactly the pixels whose host-built
+    bound exceeds the threshold, up to the rounding differences of contracted
+    FMAs on the device (pixels within 1% of the threshold may go either way)."""
+    from host import pixel
+    r = case["f32"]
+    S = torch.from_numpy(np.ascontiguousarray(r["s"])).to("cuda", torch.float32)
+    Z = torch.from_numpy(np.ascontiguousarray(r["z"])).to("cuda", torch.float32)
+    ctr = torch.zeros(3, dtype=torch.int64, device="cuda")
+    ops.wishart_loglik(S, Z, N, forward=True, backward=True, counters=ctr)
+    assert ctr.tolist() == [0, 0, 0]
+    rng = np.random.default_rng(77)
+    m = launch_n
+    U = synth.haar_unitary(rng, m)
+    eig = np.stack([np.ones(m), 10.0 ** -rng.uniform(0, 2, m), 10.0 ** -rng.uniform(0, 6, m)], 1)
+    s32 = synth.pack(np.einsum("mij,mj,mkj->mik", U, eig, np.conj(U))).astype(np.float32)
+    assert np.all(oracle.pd_class(s32.astype(np.float64)) == 0)
+    det, bound = pixel.det_plain_bound_f32(s32)
+    ratio = bound.astype(np.float64) / det.astype(np.float64)
+    lo, hi = int(np.sum(ratio > 1.01e-3)), int(np.sum(ratio >= 0.99e-3))
+    assert lo > 100  # the set exercises the flag
+    St = ops.upload_planes(s32, torch.float32)
+    ctr.zero_()
+    ops.wishart_loglik(St, St, N, forward=True, backward=True, counters=ctr)
+    c = ctr.tolist()
+    assert c[0] == 0 and c[2] == 0
+    assert lo <= c[1] <= hi, (lo, c[1], hi)
+    # FP64: the same matrices widened are far inside the threshold
+    St64 = ops.upload_planes(s32.astype(np.float64), torch.float64)
+    ctr.zero_()
+    ops.wishart_loglik(St64, St64, N, forward=True, counters=ctr)
+    assert ctr.tolist() == [0, 0, 0]

@@ -101,3 +101,36 @@ def test_indefinite_with_positive_determinant_is_not_pd():
     assert np.all(det64 > 0) and np.all(st64 == 2)
     _, det32, st32, _ = pixel.adjugate_comp_f32(z.astype(np.float32))
     assert np.all(st32 == 2)
+
+
+def test_plain_det_bound_covers_true_error():
+    """The a-priori bound of the plain FP32 determinant (the Wishart term's
+    low-accuracy flag) covers the true error on hard matrices up to kappa 1e10
+    and on scaled ones whose products underflow; it is loose by construction,
+    but not absurdly so (median bound / error below 1e3 where the error is
+    not zero)."""
+    rng = np.random.default_rng(35)
+    z = hard(rng, 60000)
+    m = 20000
+    U = synth.haar_unitary(rng, m)
+    scale = 10.0 ** rng.uniform(-12, 12, m)
+    eig = np.stack([np.ones(m), 10.0 ** -rng.uniform(0, 3, m), 10.0 ** -rng.uniform(0, 8, m)], 1) * scale[:, None]
+    z = np.concatenate([z, synth.pack(np.einsum("mij,mj,mkj->mik", U, eig, np.conj(U)))], axis=1)
+    z32 = z.astype(np.float32)
+    det, bound = pixel.det_plain_bound_f32(z32)
+    _, (dh, dl) = oracle.ge128(z32.astype(np.float64))
+    err = np.abs((det.astype(np.float64) - dh) - dl)
+    assert np.all(err <= bound.astype(np.float64))
+    nz = err > 0
+    assert np.median(bound[nz] / err[nz]) < 1e3
+    # a planted mistake, the cofactors' own product magnitudes S_i left out
+    # of the bound (gamma_8 sum |x_i| |c_i| only), fails on this data: where
+    # a cofactor cancels, its rounding error dwarfs |x_i c_i|
+    w = z32.astype(np.float64)
+    a, d, f, br, bi, cr, ci, er, ei = w
+    cof = [d * f - er * er - ei * ei, cr * er + ci * ei - br * f, ci * er - cr * ei - bi * f,
+           br * er - bi * ei - cr * d, br * ei + bi * er - ci * d]
+    xs = [a, br, bi, cr, ci]
+    g8 = 8 * 2.0 ** -24 / (1 - 8 * 2.0 ** -24)
+    planted = g8 * sum(np.abs(x) * np.abs(c) for x, c in zip(xs, cof))
+    assert np.any(err > planted)
