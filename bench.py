@@ -449,7 +449,7 @@ def _batch_workload(torch, ops, dev, steps, tune_launch):
     del imgs
     n = sum(it["z"].shape[1] for it in items)
     plan = BatchPlan(items, "adjugate", "compensated", status=False)
-    g_ms = time_calls(plan.run, steps, 3, torch)
+    g_ms = time_calls(plan.run, steps, 3, torch, 0.1)
     plan.close()
     ws = torch.empty(ops.workspace_bytes(torch.float32, max(it["z"].shape[1] for it in items)) // 8 + 1,
                      dtype=torch.float64, device=dev)
@@ -459,7 +459,7 @@ def _batch_workload(torch, ops, dev, steps, tune_launch):
         for it, ob in zip(items, outs):
             ops.inv_det(it["z"], "adjugate", "compensated", inv=ob[:9], det=ob[9])
             ops.wishart_loglik(it["sigma"], it["z"], it["n_looks"], forward=True, backward=True, workspace=ws)
-    l_ms = time_calls(loop, steps, 3, torch)
+    l_ms = time_calls(loop, steps, 3, torch, 0.1)
     del outs, ws
     # the batch's mix without arithmetic: Z and S in (18 planes), inverse, det
     # and gradient out (19), over as many pixels as the 64 images hold
@@ -480,7 +480,7 @@ def _batch_workload(torch, ops, dev, steps, tune_launch):
     if tune_launch:
         t_cfg, _ = tune.tune_batch(items, reps=5)
         plan = BatchPlan(items, "adjugate", "compensated", status=False)
-        t_ms = time_calls(plan.run, steps, 3, torch)
+        t_ms = time_calls(plan.run, steps, 3, torch, 0.1)
         plan.close()
         ops.set_launch(3, torch.float32, "adjugate", "compensated", default_cfg)
         rec.update({"autotuned_graph_ms": round(t_ms, 4), "autotuned_graph_gpx_s": round(n / t_ms / 1e6, 3),

@@ -233,9 +233,11 @@ int polsar_wishart_loglik_noalloc(int dtype, int pass, int64_t n,
 /* Batched persistent launch over many images of uneven sizes: the paper's
  * closing section names, as future work, combining several matrix
  * inversions into a single inversion call; here one call (one graph launch)
- * covers every pixel of every image.  One grid walks the tiles of all
- * images; the launch and the per-image loss reduction are captured once in
- * a HIP graph.  Per image, any of: inverse/determinant of Z (ops &
+ * covers every pixel of every image.  One grid covers the tiles of all
+ * images, numbered image after image: one block per tile (the hardware
+ * dispatcher balances the blocks over the compute units) or a persistent
+ * grid that strides over them; the launch and the per-image loss reduction
+ * are captured once in a HIP graph.  Per image, any of: inverse/determinant of Z (ops &
  * POLSAR_OP_INV_DET, Alg. 2 or Alg. 1 as for polsar_inv_det), Wishart
  * forward (loss, ell) and backward (grad) of S against Z (ops &
  * POLSAR_OP_WISHART_FWD / _BWD, as for polsar_wishart_loglik).  Host array
@@ -262,8 +264,11 @@ typedef struct polsar_batch polsar_batch;
 
 /* Create: allocates device tables, a workspace and the graph (the only call
  * that allocates).  method: POLSAR_ADJUGATE or POLSAR_CHOLESKY for the inverse;
- * the launch shape is the op-3 entry of the launch table, grid_per_cu > 0
- * overrides its blocks per compute unit.  Returns POLSAR_OK and *out, or an error
+ * the launch shape is the op-3 entry of the launch table (its grid_per_cu
+ * 0: one block per tile; k > 0: a persistent grid of k blocks per compute
+ * unit); grid_per_cu > 0 here overrides the entry's.  With counters the grid
+ * is persistent, at most 16 blocks per compute unit (one set of atomics per
+ * wave).  Returns POLSAR_OK and *out, or an error
  * (no allocation left behind). */
 int polsar_batch_create(const polsar_image* imgs, int count, int dtype, int method,
                         int precision, unsigned ops, const double* grad_loss,
@@ -294,8 +299,8 @@ void polsar_streamer_destroy(polsar_streamer* s);
 /* Launch configuration of the kernels, keyed by op (0 = inv_det,
  * 1 = wishart, 2 = multilook + inv_det, 3 = batch, 4 = the copy probe,
  * 5 = wishart on images of fewer than 2^23 pixels, 6 = inv_det on images of
- * at least 2^25 pixels; ops 2, 3 and 4 take unroll 1, op 3 a persistent
- * grid, op 4 one tile per block; ops 1, 4 and 5 are keyed with method 0 and
+ * at least 2^25 pixels; ops 2, 3 and 4 take unroll 1, op 4 one tile per
+ * block; ops 1, 4 and 5 are keyed with method 0 and
  * precision 0), dtype, method, precision.
  *   block        threads per block: 64, 128 or 256
  *   unroll       vectors per thread per tile: 1, 2 or 4 (the FP32

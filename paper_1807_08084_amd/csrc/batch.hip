@@ -2,10 +2,11 @@
 //
 // The images' pixels are cut into tiles of `block` vectors (one vector per
 // lane, V pixels per vector on the 128-bit path), numbered consecutively
-// image after image.  One persistent grid (k blocks per compute unit)
-// strides over the global tile numbers; a block finds the image of its first
-// tile by binary search over the images' first tiles and moves forward from
-// there.  Per tile it loads Z once and, as the batch asks, writes the
+// image after image.  The grid has one block per tile, so the hardware
+// dispatcher hands tiles to compute units as they free up, or is a
+// persistent grid (k blocks per compute unit) that strides over the global
+// tile numbers.  A block finds the image of its first tile by binary search
+// over the images' first tiles and moves forward from there.  Per tile it loads Z once and, as the batch asks, writes the
 // inverse/determinant of Z (FP32 compensated: rejected pixels through the
 // wave's FP64 queue, as in the per-call kernel), then loads S and writes the
 // Wishart term and gradient of S against the same Z.  The descriptor table
@@ -444,8 +445,12 @@ int polsar_batch_create(const polsar_image* imgs, int count, int dtype, int meth
   const bool queued = b->op == ADJ_COMP && dtype == POLSAR_F32 && (ops & POLSAR_OP_INV_DET);
   b->lds = polsar_launch_lds_bytes(use, queued ? comp_queue_bytes(block, VW) : 0);
   b->total_tiles = tiles;
-  const int gpc = grid_per_cu > 0 ? grid_per_cu : use.grid_per_cu;
-  b->grid = (int)std::min<int64_t>(tiles, (int64_t)gpc * device_cus_b());
+  // a persistent grid of gpc blocks per compute unit, or (gpc 0) one block
+  // per tile, the hardware's dispatcher doing the balancing; with counters
+  // at most COUNTER_GRID_PER_CU blocks per CU (one set of atomics per wave)
+  int gpc = grid_per_cu > 0 ? grid_per_cu : use.grid_per_cu;
+  if (counters && (gpc == 0 || gpc > COUNTER_GRID_PER_CU)) gpc = COUNTER_GRID_PER_CU;
+  b->grid = (int)std::min<int64_t>(tiles, gpc > 0 ? (int64_t)gpc * device_cus_b() : (int64_t)INT32_MAX);
   if (hipMalloc((void**)&b->d_img, sizeof(ImgDesc) * count) != hipSuccess) { release(b); return POLSAR_E_HIP; }
   if (hipMalloc((void**)&b->d_partial, sizeof(double) * tiles) != hipSuccess) { release(b); return POLSAR_E_HIP; }
   if (hipMemcpy(b->d_img, h.data(), sizeof(ImgDesc) * count, hipMemcpyHostToDevice) != hipSuccess) {

@@ -232,6 +232,14 @@ inline size_t comp_queue_bytes(int block, int slots) {
   return entries * (QUEUE_WORDS * sizeof(float) + 1);
 }
 
+// Most blocks per CU of a launch that asks for status counters.  Each wave
+// adds its tallies to the caller's three counters with one atomic per
+// counter when it ends; with one tile per block that puts hundreds of
+// thousands of atomics on the same three addresses (6.1 ms against 0.88 ms
+// for the FP32 compensated inverse of an 8192x8192 image), so such launches
+// stride a grid of at most this many blocks per CU over the tiles instead.
+constexpr int COUNTER_GRID_PER_CU = 16;
+
 // Lanes of the fixed-order reduction kernels (the per-call Wishart loss and
 // the batch's per-image losses use the same, so their orders agree).
 constexpr int REDUCE_BLOCK = 1024;

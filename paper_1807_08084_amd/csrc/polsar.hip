@@ -636,8 +636,9 @@ polsar_launch default_launch(int op, int dtype, int method, int prec) {
              // four-look 4096x4096 image against 0.67 with 16-byte accesses and no cap)
       if (!f64 && !chol && prec == POLSAR_COMPENSATED) return polsar_launch{256, 1, 0, 1, 8, 8};
       return f64 ? polsar_launch{256, 1, 0, 1, 8, 4} : polsar_launch{128, 1, 0, 1, 16, 0};
-    case 3:  // FP32: 2 blocks per CU, the tuner's pick on the 64-image batch (36 Gpx/s, 16 per CU: 33)
-      return f64 ? polsar_launch{256, 1, 2, 1, 16, 6} : polsar_launch{256, 1, 2, 1, 16, 0};
+    case 3:  // FP32: one block of 128 lanes per tile, 8-byte accesses (64-image batch: 0.72 of HBM, against
+             // 0.67 for the best persistent grid, 2 blocks of 256 lanes per CU)
+      return f64 ? polsar_launch{256, 1, 2, 1, 16, 6} : polsar_launch{128, 1, 0, 1, 8, 0};
     case 4:  // copy probe: few waves in flight stream best
       return polsar_launch{64, 1, 0, 1, 16, 5};
     case 6:  // the inverse kernel on images of at least INV_DET_LARGE pixels
@@ -698,7 +699,6 @@ bool valid_launch(const polsar_launch& c, int op) {
   if (c.unroll != 1 && c.unroll != 2 && !((op == 0 || op == 6) && c.unroll == 4)) return false;
   if ((op == 2 || op == 3 || op == 4) && c.unroll != 1) return false;
   if (op == 4 && c.grid_per_cu != 0) return false;
-  if (op == 3 && c.grid_per_cu == 0) return false;
   if (c.grid_per_cu < 0 || c.grid_per_cu > 64) return false;
   if (c.nontemporal != 0 && c.nontemporal != 1) return false;
   if (c.vector_bytes != 16 && c.vector_bytes != 8) return false;
@@ -718,15 +718,10 @@ int device_cus() {
   return cached[dev];
 }
 
-// Blocks of a launch over `tiles` tiles.  Each wave adds its status tallies
-// to the caller's three counters with one atomic per counter when it ends;
-// with one tile per block that puts hundreds of thousands of atomics on the
-// same three addresses (6.1 ms against 0.88 ms for the FP32 compensated
-// inverse of an 8192x8192 image), so calls that ask for counters stride a
-// grid of at most COUNTER_GRID_PER_CU blocks per CU over the tiles instead.
-// Pixels are independent and the Wishart partial sums are kept per tile, so
-// results do not depend on the grid.
-constexpr int COUNTER_GRID_PER_CU = 16;
+// Blocks of a launch over `tiles` tiles: the launch's persistent grid, or
+// one block per tile, and at most COUNTER_GRID_PER_CU blocks per CU when the
+// call asks for counters.  Pixels are independent and the Wishart partial
+// sums are kept per tile, so results do not depend on the grid.
 int64_t launch_grid(const polsar_launch& c, int64_t tiles, bool counters) {
   int gpc = c.grid_per_cu;
   if (counters && (gpc == 0 || gpc > COUNTER_GRID_PER_CU)) gpc = COUNTER_GRID_PER_CU;

@@ -74,14 +74,17 @@ def tune_multilook(looks: torch.Tensor, n_looks: int, method: str = "adjugate", 
 
 
 def tune_batch(items, method: str = "adjugate", precision: str = "compensated", reps: int = 5):
-    """Sweep the batch launch (block, blocks per CU, access width); each
+    """Sweep the batch launch (block; one block per tile or a persistent
+    grid of g blocks per CU; access width; resident-block cap); each
     candidate builds its own plan (and graph)."""
     from .batch import BatchPlan
     dtype = items[0]["z"].dtype
     best, best_ms = None, float("inf")
-    for b, g, vb, bpc in itertools.product((64, 128, 256), (2, 4, 8, 16, 32, 64), (16, 8), (0, 2, 4, 6)):
+    for b, g, vb, bpc in itertools.product((64, 128, 256), (0, 2, 4, 8), (16, 8), (0, 4, 8, 16)):
         if bpc and g > bpc:
             continue  # a persistent grid larger than what can be resident
+        if bpc * b > 2048:
+            continue  # more lanes than a CU holds
         cfg = dict(block=b, unroll=1, grid_per_cu=g, nontemporal=1, vector_bytes=vb, blocks_per_cu=bpc)
         ops.set_launch(3, dtype, method, precision, cfg)
         plan = BatchPlan(items, method, precision, status=False)

@@ -106,8 +106,11 @@ def test_launch_table(lib):
     assert lib.polsar_set_launch(0, L.F32, L.ADJUGATE, L.PLAIN, ctypes.byref(bad)) == L.E_ARG
     bad = L.Launch(block=128, unroll=2, grid_per_cu=8, nontemporal=1, vector_bytes=16, blocks_per_cu=0)
     assert lib.polsar_set_launch(3, L.F32, L.ADJUGATE, L.PLAIN, ctypes.byref(bad)) == L.E_ARG    # batch: unroll 1
-    bad = L.Launch(block=128, unroll=1, grid_per_cu=0, nontemporal=1, vector_bytes=16, blocks_per_cu=0)
-    assert lib.polsar_set_launch(3, L.F32, L.ADJUGATE, L.PLAIN, ctypes.byref(bad)) == L.E_ARG    # batch: persistent
+    keep = L.Launch()
+    assert lib.polsar_get_launch(3, L.F32, L.ADJUGATE, L.PLAIN, ctypes.byref(keep)) == L.OK
+    tile = L.Launch(block=128, unroll=1, grid_per_cu=0, nontemporal=1, vector_bytes=16, blocks_per_cu=0)
+    assert lib.polsar_set_launch(3, L.F32, L.ADJUGATE, L.PLAIN, ctypes.byref(tile)) == L.OK  # batch: one block per tile
+    assert lib.polsar_set_launch(3, L.F32, L.ADJUGATE, L.PLAIN, ctypes.byref(keep)) == L.OK
     good = L.Launch(block=128, unroll=2, grid_per_cu=4, nontemporal=0, vector_bytes=8, blocks_per_cu=4)
     assert lib.polsar_set_launch(0, L.F64, L.CHOLESKY, L.PLAIN, ctypes.byref(good)) == L.OK
     got = L.Launch()

@@ -1,4 +1,4 @@
-"""Batched persistent launch (one HIP graph) against the per-image calls and
+"""Batched launch over many images (one HIP graph) against the per-image calls and
 the oracle: images of uneven sizes with 2x4 regions, lam in [1e-2, 1], N in
 {3, 4, 8, 16} (the first images of the 64-image recipe, seed 7, plus ragged
 odd-sized images)."""
@@ -114,3 +114,22 @@ def test_batch_inv_only_and_cholesky(ops):
         inv, det, st = ops.inv_det(im["z"], "cholesky", "plain", status=True)
         assert torch.equal(plan.inv[i], inv) and torch.equal(plan.det[i], det) and torch.equal(plan.status[i], st)
     plan.close()
+
+
+def test_batch_grid_kinds_agree(ops):
+    """One block per tile (the FP32 default) and a persistent grid give the
+    same bits: every output, and the losses (partial sums are per tile)."""
+    from paper_1807_08084_amd.batch import BatchPlan
+    imgs = _images(torch.float32)
+    assert ops.get_launch(3, torch.float32, "adjugate", "compensated")["grid_per_cu"] == 0
+    a = BatchPlan(imgs, "adjugate", "compensated", ell=True)
+    b = BatchPlan(imgs, "adjugate", "compensated", ell=True, grid_per_cu=2)
+    a.run()
+    b.run()
+    torch.cuda.synchronize()
+    for i in range(len(imgs)):
+        for x, y in ((a.inv, b.inv), (a.det, b.det), (a.status, b.status), (a.grad, b.grad), (a.ell, b.ell)):
+            assert torch.equal(x[i], y[i])
+    assert torch.equal(a.loss, b.loss)
+    a.close()
+    b.close()
