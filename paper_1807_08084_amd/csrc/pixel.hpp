@@ -378,6 +378,22 @@ PX_HD void look_accumulate(const T s[6], double acc[9]) {
   acc[8] += vi * wr - vr * wi;
 }
 
+// The first look of a sum: its contribution itself (equal to adding it to
+// zero with look_accumulate_chained).
+template <class T>
+PX_HD void look_first(const T s[6], double acc[9]) {
+  const double hr = s[0], hi = s[1], vr = s[2], vi = s[3], wr = s[4], wi = s[5];
+  acc[0] = fma_(hi, hi, hr * hr);
+  acc[1] = fma_(vi, vi, vr * vr);
+  acc[2] = fma_(wi, wi, wr * wr);
+  acc[3] = fma_(hi, vi, hr * vr);
+  acc[4] = fma_(-hr, vi, hi * vr);
+  acc[5] = fma_(hi, wi, hr * wr);
+  acc[6] = fma_(-hr, wi, hi * wr);
+  acc[7] = fma_(vi, wi, vr * wr);
+  acc[8] = fma_(-vr, wi, vi * wr);
+}
+
 template <class T>
 PX_HD void look_accumulate_chained(const T s[6], double acc[9]) {
   const double hr = s[0], hi = s[1], vr = s[2], vi = s[3], wr = s[4], wi = s[5];

@@ -256,17 +256,30 @@ __global__ __launch_bounds__(256) void k_multilook(MultilookArgs a) {
 // rows and walks down it one input row at a time: the row's single-look
 // pixels (with an R-pixel halo each side, zeros outside the image, which add
 // nothing) are staged in LDS in FP64, double-buffered, while the next row is
-// being loaded; each lane forms the sum of its 2R+1 horizontal neighbours'
-// outer products in FP64 (exact products for FP32 input) and keeps the last
-// 2R+1 such row sums in registers, oldest first (shifted down one slot per
-// row, so every index is fixed at compile time and the loop body, with its
-// inverse, exists once).  Once a lane holds the rows of its output's window
-// it adds them in ascending row order, scales by the reciprocal of the
-// clipped window size (within an FP64 ulp of the quotient), rounds Z to the
-// storage type (optionally stores it) and inverts it with the per-pixel
-// function of the per-call kernel.  Each row sum is formed once per strip,
-// so the work per output is (2R+1) outer products and 2R+1 additions of
-// nine components, plus the halo rows of the strip.
+// being loaded; each lane forms the sum of its K = 2R+1 horizontal
+// neighbours' outer products in FP64 (exact products for FP32 input) and
+// adds K consecutive row sums for its output.  Each output is scaled by the
+// reciprocal of the clipped window size (within an FP64 ulp of the
+// quotient), rounded to the storage type (optionally stored) and inverted
+// with the per-pixel function of the per-call kernel.
+//
+// The vertical sums, without subtraction (so every window keeps the error
+// bound of a plain sum of its own terms), two ways:
+// * K <= 5 (k_boxcar_shift): the last K row sums sit in registers, oldest
+//   first, shifted down one slot per row, and the K of a window are added
+//   in ascending row order.
+// * K = 7 (k_boxcar_grouped): rows are taken in groups of K, row j of a
+//   group going to slot j (the loop over a group is unrolled, so slot
+//   indices are compile-time constants and nothing is shifted).  The window
+//   that ends at row j of a group is the previous group's rows j+1 .. K-1
+//   plus this group's rows 0 .. j: a running prefix sum of this group plus
+//   the previous group's suffix sum from row j+1, which the slots hold once
+//   a group ends and its suffix sums are formed in place (the scheme of van
+//   Herk, and of Gil and Werman, for running maxima, with + for max): about
+//   three additions of nine components per output for any K, instead of
+//   K-1 plus the shift (7x7 on a 4096^2 image: 44.6-45.3 against 41.6
+//   Gpx/s).  The group's K inlined inverses need more registers than the
+//   shifted ring's one: at K = 3 and 5 they spilled and ran 25-35% slower.
 constexpr int BOX_TW = 64, BOX_MAX_R = 3;
 // Strip height: each strip re-forms the row sums of its 2R halo rows, so
 // wide windows take taller strips (7x7: 64 rows 4% faster than 32); 3x3
@@ -287,93 +300,179 @@ struct BoxArgs {
   int64_t nbx;  // blocks across the image
 };
 
+// The block's strip and this lane's column.
+template <int R>
+struct BoxStrip {
+  int64_t x0, ys, y_first, y_last, gx, cols;
+  __device__ BoxStrip(const BoxArgs& a) {
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t bx = t % a.nbx, by = t / a.nbx;
+    x0 = bx * BOX_TW;
+    ys = by * box_strip(R);
+    const int64_t ye = ys + box_strip(R) < a.H ? ys + box_strip(R) : a.H;
+    y_first = ys - R;  // rows staged (outside the image: zeros)
+    y_last = ye - 1 + R;
+    gx = x0 + threadIdx.x;
+    cols = (gx + R < a.W ? gx + R : a.W - 1) - (gx - R > 0 ? gx - R : 0) + 1;
+  }
+};
+
+// The staged pixels of input row y this lane loads.  Pixels outside the
+// image load pixel 0 instead (every load is in bounds and unconditional, so
+// the loads stay in flight while the current row is summed) and are staged
+// as zeros, which add nothing.
+template <class T, int R, int P>
+__device__ __forceinline__ void box_load_row(const BoxArgs& a, int64_t x0, int64_t y, T (&v)[P][6], bool (&ok)[P]) {
+  constexpr int SW = BOX_TW + 2 * R;
+  const T* __restrict__ S = (const T*)a.s;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int col = threadIdx.x + p * BOX_TW;
+    const int64_t x = x0 - R + col;
+    ok[p] = col < SW && y >= 0 && y < a.H && x >= 0 && x < a.W;
+    const int64_t i = ok[p] ? y * a.W + x : 0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[p][k] = S[k * a.sp + i];
+  }
+}
+
+// Stage the loaded row in an LDS row buffer, in FP64.
+template <class T, int R, int P>
+__device__ __forceinline__ void box_stage(double (*row)[BOX_TW + 2 * R], const T (&v)[P][6], const bool (&ok)[P]) {
+  constexpr int SW = BOX_TW + 2 * R;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int col = threadIdx.x + p * BOX_TW;
+    if (col < SW)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) row[k][col] = ok[p] ? (double)v[p][k] : 0.0;
+  }
+}
+
+// This lane's row sum of the staged row: its K horizontal neighbours.
+template <int R>
+__device__ __forceinline__ void box_row_sum(double (*row)[BOX_TW + 2 * R], double (&sum)[9]) {
+  double s6[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s6[k] = row[k][threadIdx.x];
+  px::look_first(s6, sum);
+#pragma unroll
+  for (int dx = 1; dx < 2 * R + 1; ++dx) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s6[k] = row[k][threadIdx.x + dx];
+    px::look_accumulate_chained(s6, sum);
+  }
+}
+
+// Output row yo of this lane from its window sum: Z, inverse, det, status.
 template <class T, int OP, int R>
-__global__ __launch_bounds__(BOX_TW) void k_boxcar(BoxArgs a) {
+__device__ __forceinline__ void box_output(const BoxArgs& a, const BoxStrip<R>& b, int64_t yo, const double (&w)[9],
+                                           unsigned& c0, unsigned& c1, unsigned& c2) {
+  const int64_t rows = (yo + R < a.H ? yo + R : a.H - 1) - (yo - R > 0 ? yo - R : 0) + 1;
+  const double rcp = 1.0 / (double)(rows * b.cols);
+  T zz[9], xx[9], dt;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) zz[c] = (T)(w[c] * rcp);
+  const int64_t i = yo * a.W + b.gx;
+  if (a.z)
+#pragma unroll
+    for (int c = 0; c < 9; ++c) ((T*)a.z)[c * a.zp + i] = zz[c];
+  const int st_px = run_pixel<T, OP>(zz, xx, dt);
+  tally(st_px, c0, c1, c2);
+  if (a.inv)
+#pragma unroll
+    for (int c = 0; c < 9; ++c) ((T*)a.inv)[c * a.ip + i] = xx[c];
+  if (a.det) ((T*)a.det)[i] = dt;
+  if (a.status) a.status[i] = (uint8_t)st_px;
+}
+
+template <class T, int OP, int R>
+__global__ __launch_bounds__(BOX_TW) void k_boxcar_shift(BoxArgs a) {
   constexpr int K = 2 * R + 1, SW = BOX_TW + 2 * R;
   constexpr int P = (SW + BOX_TW - 1) / BOX_TW;  // staged pixels per lane and row
-  __shared__ double row[2][6][SW];  // staged in FP64 (exact for FP32 input)
-  const T* __restrict__ S = (const T*)a.s;
-  const int lane = threadIdx.x;
-  const int64_t t = xcd_tile(blockIdx.x, gridDim.x);
-  const int64_t bx = t % a.nbx, by = t / a.nbx;
-  constexpr int STRIP = box_strip(R);
-  const int64_t x0 = bx * BOX_TW, ys = by * STRIP;
-  const int64_t ye = ys + STRIP < a.H ? ys + STRIP : a.H;
-  const int64_t y_first = ys - R, y_last = ye - 1 + R;  // rows staged (outside the image: zeros)
-  const int64_t gx = x0 + lane;
-  const int64_t cols = (gx + R < a.W ? gx + R : a.W - 1) - (gx - R > 0 ? gx - R : 0) + 1;
-  auto load_row = [&](int64_t y, T (&v)[P][6]) {
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-#pragma unroll
-      for (int k = 0; k < 6; ++k) v[p][k] = T(0);
-      const int col = lane + p * BOX_TW;
-      const int64_t x = x0 - R + col;
-      if (col < SW && y >= 0 && y < a.H && x >= 0 && x < a.W) {
-        const int64_t i = y * a.W + x;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) v[p][k] = S[k * a.sp + i];
-      }
-    }
-  };
+  __shared__ double row[2][6][SW];
+  const BoxStrip<R> b(a);
   double ring[K][9];  // row sums of rows y - 2R .. y, oldest first
 #pragma unroll
   for (int m = 0; m < K; ++m)
 #pragma unroll
     for (int c = 0; c < 9; ++c) ring[m][c] = 0.0;
   T pre[P][6];
+  bool pok[P];
   unsigned c0 = 0, c1 = 0, c2 = 0;
-  load_row(y_first, pre);
+  box_load_row<T, R, P>(a, b.x0, b.y_first, pre, pok);
 #pragma unroll 1
-  for (int64_t y = y_first; y <= y_last; ++y) {  // the same for every lane of the block
-    const int b = (int)((y - y_first) & 1);
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const int col = lane + p * BOX_TW;
-      if (col < SW)
-#pragma unroll
-        for (int k = 0; k < 6; ++k) row[b][k][col] = (double)pre[p][k];
-    }
+  for (int64_t y = b.y_first; y <= b.y_last; ++y) {  // the same for every lane of the block
+    const int buf = (int)((y - b.y_first) & 1);
+    box_stage<T, R, P>(row[buf], pre, pok);
     __syncthreads();
-    if (y + 1 <= y_last) load_row(y + 1, pre);  // in flight while this row is summed
+    if (y + 1 <= b.y_last) box_load_row<T, R, P>(a, b.x0, y + 1, pre, pok);  // in flight while this row is summed
 #pragma unroll
     for (int m = 0; m + 1 < K; ++m)
 #pragma unroll
       for (int c = 0; c < 9; ++c) ring[m][c] = ring[m + 1][c];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) ring[K - 1][c] = 0.0;
-#pragma unroll
-    for (int dx = 0; dx < K; ++dx) {
-      double s6[6];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) s6[k] = row[b][k][lane + dx];
-      px::look_accumulate_chained(s6, ring[K - 1]);
-    }
+    box_row_sum<R>(row[buf], ring[K - 1]);
     // output row y - R, whose window rows y - 2R .. y the ring now holds
     const int64_t yo = y - R;
-    if (yo >= ys && gx < a.W) {
-      double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (yo >= b.ys && b.gx < a.W) {
+      double w[9];
 #pragma unroll
-      for (int m = 0; m < K; ++m)
+      for (int c = 0; c < 9; ++c) w[c] = ring[0][c];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) acc[c] += ring[m][c];
-      const int64_t rows = (yo + R < a.H ? yo + R : a.H - 1) - (yo - R > 0 ? yo - R : 0) + 1;
-      const double rcp = 1.0 / (double)(rows * cols);
-      T zz[9], xx[9], dt;
+      for (int m = 1; m < K; ++m)
 #pragma unroll
-      for (int c = 0; c < 9; ++c) zz[c] = (T)(acc[c] * rcp);
-      const int64_t i = yo * a.W + gx;
-      if (a.z)
-#pragma unroll
-        for (int c = 0; c < 9; ++c) ((T*)a.z)[c * a.zp + i] = zz[c];
-      const int st_px = run_pixel<T, OP>(zz, xx, dt);
-      tally(st_px, c0, c1, c2);
-      if (a.inv)
-#pragma unroll
-        for (int c = 0; c < 9; ++c) ((T*)a.inv)[c * a.ip + i] = xx[c];
-      if (a.det) ((T*)a.det)[i] = dt;
-      if (a.status) a.status[i] = (uint8_t)st_px;
+        for (int c = 0; c < 9; ++c) w[c] += ring[m][c];
+      box_output<T, OP, R>(a, b, yo, w, c0, c1, c2);
     }
+  }
+  if (a.counters) flush_counters(a.counters, c0, c1, c2);
+}
+
+template <class T, int OP, int R>
+__global__ __launch_bounds__(BOX_TW) void k_boxcar_grouped(BoxArgs a) {
+  constexpr int K = 2 * R + 1, SW = BOX_TW + 2 * R;
+  constexpr int P = (SW + BOX_TW - 1) / BOX_TW;
+  __shared__ double row[2][6][SW];
+  const BoxStrip<R> b(a);
+  // slot j: the row sum of row j of the current group, or, once the group is
+  // done, the sum of its rows j .. K-1
+  double ring[K][9];
+#pragma unroll
+  for (int m = 0; m < K; ++m)
+#pragma unroll
+    for (int c = 0; c < 9; ++c) ring[m][c] = 0.0;
+  T pre[P][6];
+  bool pok[P];
+  unsigned c0 = 0, c1 = 0, c2 = 0;
+  box_load_row<T, R, P>(a, b.x0, b.y_first, pre, pok);
+#pragma unroll 1
+  for (int64_t y0 = b.y_first; y0 <= b.y_last; y0 += K) {  // the same for every lane of the block
+    double run[9];  // prefix sum of the group's row sums
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int64_t y = y0 + j;
+      if (y > b.y_last) break;
+      const int buf = (int)((y - b.y_first) & 1);
+      box_stage<T, R, P>(row[buf], pre, pok);
+      __syncthreads();
+      if (y + 1 <= b.y_last) box_load_row<T, R, P>(a, b.x0, y + 1, pre, pok);
+      box_row_sum<R>(row[buf], ring[j]);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) run[c] = j == 0 ? ring[0][c] : run[c] + ring[j][c];
+      // output row y - R: window rows y - 2R .. y
+      const int64_t yo = y - R;
+      if (yo >= b.ys && b.gx < a.W) {
+        double w[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) w[c] = j + 1 < K ? ring[j + 1 < K ? j + 1 : 0][c] + run[c] : run[c];
+        box_output<T, OP, R>(a, b, yo, w, c0, c1, c2);
+      }
+    }
+    // the group's suffix sums, for the next group's windows
+#pragma unroll
+    for (int j = K - 2; j >= 0; --j)
+#pragma unroll
+      for (int c = 0; c < 9; ++c) ring[j][c] += ring[j + 1][c];
   }
   if (a.counters) flush_counters(a.counters, c0, c1, c2);
 }
@@ -923,7 +1022,10 @@ template <class T, int OP, int R>
 hipError_t go_boxcar_r(BoxArgs& a, hipStream_t s) {
   a.nbx = (a.W + BOX_TW - 1) / BOX_TW;
   const int64_t nby = (a.H + box_strip(R) - 1) / box_strip(R);
-  hipLaunchKernelGGL((k_boxcar<T, OP, R>), dim3((unsigned)(a.nbx * nby)), dim3(BOX_TW), 0, s, a);
+  if constexpr (R <= 2)
+    hipLaunchKernelGGL((k_boxcar_shift<T, OP, R>), dim3((unsigned)(a.nbx * nby)), dim3(BOX_TW), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_boxcar_grouped<T, OP, R>), dim3((unsigned)(a.nbx * nby)), dim3(BOX_TW), 0, s, a);
   return hipGetLastError();
 }
 

@@ -157,30 +157,36 @@ ROW_KERNELS = [
     ("k_inv_det<float, 3, 2, 1, true>", "FP32 plain Cholesky", 36, 40),
     ("k_wishart<float, 4, 1, true>", "FP32 Wishart fwd+bwd", 72, 36),
     ("k_wishart<double, 1, 1, true>", "FP64 Wishart fwd+bwd", 144, 72),
-    ("k_boxcar<float, 1, 1>", "boxcar 3x3 (halo rows: +2/32 of the reads)", 24, 40),
-    ("k_boxcar<float, 1, 3>", "boxcar 7x7 (halo rows: +6/64 of the reads)", 24, 40),
+    ("k_boxcar_shift<float, 1, 1>", "boxcar 3x3 (halo rows: +2/32 of the reads)", 24, 40),
+    ("k_boxcar_grouped<float, 1, 3>", "boxcar 7x7 (halo rows: +6/64 of the reads)", 24, 40),
+    ("k_nlm<float, 0, 1>", "nonlocal means 23x23, KL (Z and its inverse in, filtered Z out)", 72, 36),
+    ("k_nlm<float, 1, 1>", "nonlocal means 23x23, Bhattacharyya (Z and det in)", 40, 36),
 ]
 
 
 def traffic_rows(fetch_db: str, write_db: str, out: str, command: str, n_px: int = 4096 * 4096) -> None:
     """HBM bytes per pixel of the bench rows' kernels (FETCH_SIZE / WRITE_SIZE
-    per dispatch, scaled by the one-plane copy probe) against their
-    algorithmic bytes.  Each kernel's dispatches at its most frequent grid
-    size are used (the image; the streamer's chunks share kernel names)."""
+    per dispatch, scaled by the one-plane copy probe: 4 bytes per pixel of
+    the probe's grid) against their algorithmic bytes.  Each kernel's
+    dispatches at its most frequent grid size are used (the image; the
+    streamer's chunks share kernel names)."""
     f = _counter(fetch_db, "FETCH_SIZE", main_grid=True)
     w = _counter(write_db, "WRITE_SIZE", main_grid=True)
+    fg = _counter_grid(fetch_db, "FETCH_SIZE")
 
     def one_plane_copy(k):
         args = k[k.find("<") + 1:k.rfind(">")].split(", ")
         return k.startswith("k_copy<float,") and args[2:4] == ["1", "1"]
     probe = next(k for k in f if one_plane_copy(k))
-    f_scale = 4 * n_px / (f[probe] * 1024)
-    w_scale = 4 * n_px / (w[probe] * 1024)
+    probe_px = fg[probe] * int(probe[probe.find("<") + 1:].split(", ")[1])  # threads x pixels per lane
+    f_scale = 4 * probe_px / (f[probe] * 1024)
+    w_scale = 4 * probe_px / (w[probe] * 1024)
     with open(out, "w") as fh:
         fh.write("# HBM traffic per pixel of the bench rows' kernels, 4096x4096 image\n")
         fh.write(f"# command: {command}\n")
         fh.write(_hash_lines())
-        fh.write(f"# scales from the one-plane copy probe: FETCH_SIZE x{f_scale:.5f}, WRITE_SIZE x{w_scale:.5f}\n")
+        fh.write(f"# scales from the one-plane copy probe ({probe_px} pixels): FETCH_SIZE x{f_scale:.5f}, "
+                 f"WRITE_SIZE x{w_scale:.5f}\n")
         fh.write(f"{'kernel':36s} {'read B/px':>10s} {'alg':>5s} {'ratio':>7s} {'write B/px':>11s} {'alg':>5s} "
                  f"{'ratio':>7s}  what\n")
         for name, what, ar, aw in ROW_KERNELS:
