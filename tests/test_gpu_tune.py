@@ -64,3 +64,33 @@ def test_tune_wishart_and_json_round_trip(ops, tmp_path):
         assert ops.get_launch(op, torch.float32, "adjugate", "plain") == cfg
     finally:
         ops.set_launch(op, torch.float32, "adjugate", "plain", keep)
+
+
+def test_tune_batch_installs_a_valid_launch(ops):
+    """The batch tuner's pick is installed as the op-3 entry (so it passed
+    the launch checks), and a plan built on it gives the per-image calls'
+    results bit for bit (the first three images of the 64-image recipe)."""
+    from paper_1807_08084_amd import tune
+    from paper_1807_08084_amd.batch import BatchPlan
+    items = []
+    for im in synth.workload_batch(max_images=3):
+        z = im.planes.reshape(9, -1)
+        items.append({"z": torch.from_numpy(z).to("cuda", torch.float32),
+                      "sigma": torch.from_numpy(synth.wishart_sigma0(z)).to("cuda", torch.float32),
+                      "n_looks": float(im.n_looks)})
+    keep = ops.get_launch(3, torch.float32, "adjugate", "compensated")
+    try:
+        cfg, ms = tune.tune_batch(items, reps=2)
+        assert ms > 0 and ops.get_launch(3, torch.float32, "adjugate", "compensated") == cfg
+        plan = BatchPlan(items, "adjugate", "compensated")
+        plan.run()
+        torch.cuda.synchronize()
+        for i, it in enumerate(items):
+            inv, det, st = ops.inv_det(it["z"], "adjugate", "compensated", status=True)
+            _, grad, _ = ops.wishart_loglik(it["sigma"], it["z"], it["n_looks"], forward=True, backward=True)
+            torch.cuda.synchronize()
+            assert torch.equal(plan.inv[i], inv) and torch.equal(plan.det[i], det)
+            assert torch.equal(plan.status[i], st) and torch.equal(plan.grad[i], grad)
+        plan.close()
+    finally:
+        ops.set_launch(3, torch.float32, "adjugate", "compensated", keep)
