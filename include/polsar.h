@@ -218,11 +218,11 @@ size_t polsar_wishart_workspace_bytes(int dtype, int64_t n);
  * same kernels and launch, so the same results bit for bit.  The call
  * allocates nothing (no hipMalloc, no library allocation).  The forward pass
  * takes at most 2^20 tiles of the launch in use: at the default launches
- * FP32 images of up to 2^28 pixels (2^30 with 16-byte aligned planes) and
- * FP64 images of up to 2^27; beyond that POLSAR_E_WORKSPACE, before any HIP
- * call.  Every call on
- * one GPU shares its array: calls that overlap in time on one GPU (other
- * streams, other host threads) race and must not be issued. */
+ * FP32 images of up to 2^28 pixels (2^29 where the planes allow vector
+ * accesses) and FP64 images of up to 2^27; beyond that POLSAR_E_WORKSPACE,
+ * before any HIP call.  Every call on one GPU shares its array: calls that
+ * overlap in time on one GPU (other streams, other host threads) race and
+ * must not be issued. */
 int polsar_wishart_loglik_noalloc(int dtype, int pass, int64_t n,
                                   const void* sigma, int64_t s_pitch,
                                   const void* z, int64_t z_pitch, double n_looks,

@@ -727,10 +727,13 @@ constexpr int64_t INV_DET_LARGE = int64_t(1) << 25;
 polsar_launch default_launch(int op, int dtype, int method, int prec) {
   const bool f64 = dtype == POLSAR_F64, chol = method == POLSAR_CHOLESKY;
   switch (op) {
-    case 1:
-      return f64 ? polsar_launch{128, 1, 0, 1, 8, 4} : polsar_launch{256, 1, 0, 1, 16, 0};
-    case 5:  // the Wishart kernel below WISHART_SMALL pixels: more, smaller tiles
-      return f64 ? polsar_launch{128, 1, 0, 1, 8, 4} : polsar_launch{128, 1, 0, 1, 8, 5};
+    case 1:  // FP32: 8-byte accesses, at most 4 blocks per CU (4096^2: 0.774 of HBM against 0.763 with
+             // 16-byte accesses and no cap; 8192^2: 0.738 against 0.684).  FP64 shapes with 256-lane blocks
+             // reach 0.78 on 4096^2 but fall to 0.58 on 8192^2; 128 lanes, 4 per CU: 0.754 and 0.685
+      return f64 ? polsar_launch{128, 1, 0, 1, 8, 4} : polsar_launch{256, 1, 0, 1, 8, 4};
+    case 5:  // the Wishart kernel below WISHART_SMALL pixels: more, smaller tiles (FP64 on 2048^2: 5 blocks
+             // per CU 0.757 of HBM, the Wishart tuner's pick in every bench run, against 0.689 with 4)
+      return f64 ? polsar_launch{128, 1, 0, 1, 8, 5} : polsar_launch{128, 1, 0, 1, 8, 5};
     case 2:  // FP32 compensated: 8-byte accesses, at most 8 blocks of 256 lanes per CU (0.75 of HBM on the
              // four-look 4096x4096 image against 0.67 with 16-byte accesses and no cap)
       if (!f64 && !chol && prec == POLSAR_COMPENSATED) return polsar_launch{256, 1, 0, 1, 8, 8};
