@@ -630,6 +630,14 @@ def main():
     }
     if not args.no_rows:
         ksteps = max(10, args.steps // 2)
+        # the step's access mix without arithmetic on the same image (9 planes
+        # in, 10 out; launch swept): the practical streaming ceiling at 8192^2
+        c_ms, c_cfg = copy_ceiling(torch, ops, z32, outp, 9, 10, n_px, ksteps)
+        out["copy_ceiling_8192"] = {"kernel": "9->10 plane copy of the step's image", "ms": round(c_ms, 4),
+                                    "GB_s": round(BYTES_PER_PX["f32"] * n_px / c_ms / 1e6, 1),
+                                    "frac_hbm": round(BYTES_PER_PX["f32"] * n_px / c_ms / 1e6 / PEAK_HBM_GBS, 4),
+                                    "launch": c_cfg, "step_frac_of_ceiling": round(c_ms / ms, 4),
+                                    "launch_median_frac_of_ceiling": round(c_ms / launch_stats["median"], 4)}
         out["speedup_adjugate_vs_cholesky"] = {}
         if not args.no_8192_rows:
             # the other forms on the same image; the default step again
