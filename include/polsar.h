@@ -230,7 +230,7 @@ int polsar_wishart_loglik_noalloc(int dtype, int pass, int64_t n,
                                   void* grad, int64_t g_pitch,
                                   unsigned long long* counters, void* stream);
 
-/* Batched persistent launch over many images of uneven sizes: the paper's
+/* Batched launch over many images of uneven sizes: the paper's
  * closing section names, as future work, combining several matrix
  * inversions into a single inversion call; here one call (one graph launch)
  * covers every pixel of every image.  One grid covers the tiles of all

@@ -1,4 +1,4 @@
-"""Batched persistent launch over many images (one HIP graph)."""
+"""Batched launch over many images (one HIP graph)."""
 from __future__ import annotations
 
 import ctypes
@@ -11,7 +11,8 @@ from .ops import _METHODS, _PRECS, _dtype_code, _planes, _ptr, _stream, empty_pl
 
 class BatchPlan:
     """Inverse/determinant of each image's Z and the Wishart term/gradient of
-    its S against the same Z, for many images in one persistent launch.
+    its S against the same Z, for many images in one launch (one block per
+    tile, or a persistent grid: the op-3 entry of the launch table).
 
     ``images``: list of dicts with keys ``z`` (9, ...) and, for the Wishart
     ops, ``sigma`` (same shape) and ``n_looks``.  Output tensors are allocated

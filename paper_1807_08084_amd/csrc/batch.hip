@@ -1,4 +1,4 @@
-// Batched persistent launch over many images of uneven sizes.
+// Batched launch over many images of uneven sizes.
 //
 // The images' pixels are cut into tiles of `block` vectors (one vector per
 // lane, V pixels per vector on the 128-bit path), numbered consecutively

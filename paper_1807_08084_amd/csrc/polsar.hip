@@ -703,10 +703,9 @@ std::map<std::tuple<int, int, int, int>, polsar_launch> g_cfg;
 // non-temporal (streaming) loads and stores.
 // The Wishart kernel in FP64 with 16-byte accesses needs all 256 VGPRs (one
 // wave per SIMD); with 8-byte accesses it runs at three waves per SIMD and
-// 20% faster; capped at 4 blocks of 128 lanes per CU it gains another 6-15%
-// on the 2048x2048 image and stays within 2% of the best on 4096x4096.  The batch kernel (op 3) is a persistent grid.  blocks_per_cu
-// caps the resident blocks: with 4-5 waves per CU the 19 concurrent plane
-// streams of a 3x3 inverse reach ~82% of HBM peak, with more they contend.
+// 20% faster.  blocks_per_cu caps the resident blocks: with 4-5 waves per CU
+// the 19 concurrent plane streams of a 3x3 inverse reach ~82% of HBM peak,
+// with more they contend.
 // Images below this many pixels take the Wishart kernel's launch from op 5
 // of the table instead of op 1: on 2048x2048 (2^22 pixels) 8-byte accesses
 // in 128-lane blocks, at most 5 per CU, ran the FP32 fused forward+backward
