@@ -287,8 +287,9 @@ def equal_accuracy(rows: dict) -> dict:
 
 def scale_rows(torch, ops, dev, img, steps: int) -> dict:
     """The 4096x4096 image: all inverse forms, the copy ceiling, the Wishart
-    forward+backward, the fused multilook front ends, the boxcar multilook,
-    the nonlocal-means filter and the out-of-core streamer."""
+    forward+backward, the fused multilook front ends, three-band
+    block-diagonal pixels, the boxcar multilook, the nonlocal-means filter
+    and the out-of-core streamer."""
     from paper_1807_08084_amd import synth
     z64 = img.planes.reshape(9, -1)
     n_px = z64.shape[1]
@@ -332,6 +333,20 @@ def scale_rows(torch, ops, dev, img, steps: int) -> dict:
     rows["copy_24to10_f32"] = rate_row(n_px, c_ms, 136, launch=ccfg)
     del dst10
     del lk
+    torch.cuda.empty_cache()
+    # block-diagonal pixels of three bands (multifrequency), FP32 compensated:
+    # band 0 the image, bands 1 and 2 the image with its pixels rotated by a
+    # third and two thirds (other matrices at every pixel); 27 planes in, 27
+    # inverse planes and the determinant product out: 220 B per px
+    bands = np.concatenate([np.roll(z64, (b * n_px) // 3, axis=1) for b in range(3)], axis=0)
+    zb = ops.upload_planes(bands.astype(np.float32), torch.float32, dev)
+    del bands
+    b_ms = time_calls(lambda: ops.blockdiag_inv_det(zb, 3, "adjugate", "compensated"), steps, 3, torch, 0.1)
+    rows["blockdiag_3_bands_f32"] = rate_row(n_px, b_ms, 220, bytes_per_px=220)
+    dst28 = ops.empty_planes(28, n_px, torch.float32, dev)
+    c_ms, ccfg = copy_ceiling(torch, ops, zb, dst28, 27, 28, n_px, steps)
+    rows["copy_27to28_f32"] = rate_row(n_px, c_ms, 220, launch=ccfg)
+    del zb, dst28
     torch.cuda.empty_cache()
     # spatial (boxcar) multilook of a single-look image, 3x3 and 7x7 windows,
     # inverse + det out; 24 B in + 40 B out per px

@@ -343,8 +343,9 @@ int polsar_autotune_inv_det(int dtype, int method, int precision, int64_t n,
  * the same access pattern as the inverse kernels, for a measured ceiling of
  * each kernel's mix of plane streams: (n_in, n_out) is (9, 10) (inverse),
  * (18, 9) (Wishart forward+backward), (18, 19) (the batch: inverse and
- * Wishart), (24, 10) (four-look multilook) or (1, 1) (counter calibration);
- * planes 16-byte aligned.
+ * Wishart), (24, 10) (four-look multilook), (27, 28) (three-band
+ * block-diagonal inverse) or (1, 1) (counter calibration); planes 16-byte
+ * aligned.
  * Launch shape: op 4 of polsar_get_launch. */
 int polsar_stream_copy(int dtype, int64_t n, const void* src, int64_t src_pitch, int n_in,
                        void* dst, int64_t dst_pitch, int n_out, void* stream);

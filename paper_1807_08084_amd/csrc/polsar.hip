@@ -1482,7 +1482,7 @@ int polsar_stream_copy(int dtype, int64_t n, const void* src, int64_t src_pitch,
   if (r) return r;
   if ((r = check_planes(dst, dst_pitch, n, es))) return r;
   const bool shape_ok = (n_in == 9 && n_out == 10) || (n_in == 18 && n_out == 9) || (n_in == 18 && n_out == 19) ||
-                        (n_in == 24 && n_out == 10) || (n_in == 1 && n_out == 1);
+                        (n_in == 24 && n_out == 10) || (n_in == 27 && n_out == 28) || (n_in == 1 && n_out == 1);
   if (!shape_ok) return POLSAR_E_UNSUPPORTED;
   if (!vec_ok(src, src_pitch, es) || !vec_ok(dst, dst_pitch, es)) return POLSAR_E_ALIGN;
   if (n > 0 && overlap(span(src, n_in, src_pitch, n, es), span(dst, n_out, dst_pitch, n, es))) return POLSAR_E_ALIAS;
@@ -1510,6 +1510,7 @@ int polsar_stream_copy(int dtype, int64_t n, const void* src, int64_t src_pitch,
     else if (n_in == 18 && n_out == 9) POLSAR_COPY(T, V, 18, 9);                                              \
     else if (n_in == 18) POLSAR_COPY(T, V, 18, 19);                                                           \
     else if (n_in == 24) POLSAR_COPY(T, V, 24, 10);                                                           \
+    else if (n_in == 27) POLSAR_COPY(T, V, 27, 28);                                                           \
     else POLSAR_COPY(T, V, 1, 1);                                                                             \
   } while (0)
   if (dtype == POLSAR_F32) {

@@ -19,7 +19,7 @@ def ops():
 
 
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
-@pytest.mark.parametrize("n_in,n_out", [(9, 10), (18, 9), (18, 19), (24, 10), (1, 1)])
+@pytest.mark.parametrize("n_in,n_out", [(9, 10), (18, 9), (18, 19), (24, 10), (27, 28), (1, 1)])
 @pytest.mark.parametrize("n", [1000, 1027])
 def test_copy_probe(ops, dtype, n_in, n_out, n):
     rng = np.random.default_rng(n_in * 100 + n_out)
