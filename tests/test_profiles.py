@@ -1,4 +1,5 @@
-"""The measurement plumbing on the CPU: the profile summariser on a small
+"""The measurement plumbing on the CPU: the bench's one-GPU contract and its
+copy-ceiling sweep, the profile summariser on a small
 synthetic counter database, and the bench's lookup of the committed HBM
 traffic record (used only while it was taken on the current sources)."""
 import os
@@ -59,3 +60,41 @@ def test_bench_reads_traffic_only_for_the_current_sources(tmp_path, monkeypatch)
     assert bench.traffic_from_profiles("k_inv_det<float, ADJ_COMP>", N_PX) is None
     os.remove(rec / bench.TRAFFIC_RECORD)
     assert bench.traffic_from_profiles("k_inv_det<float, ADJ_COMP>", N_PX) is None
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: --gpus 2 exits with status 2 and says why,
+    before anything touches a GPU."""
+    import subprocess
+    import sys
+    p = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2 and "runs on one GPU" in p.stderr and p.stdout == ""
+
+
+def test_copy_ceiling_keeps_the_launch_table(monkeypatch):
+    """The bench's copy-ceiling sweep restores the probe's launch entry and
+    returns the fastest shape it timed."""
+    calls, table = [], {"cfg": {"block": 128}}
+
+    class FakeOps:
+        @staticmethod
+        def get_launch(op, dt, m, p):
+            return table["cfg"]
+
+        @staticmethod
+        def set_launch(op, dt, m, p, cfg):
+            table["cfg"] = cfg
+
+        @staticmethod
+        def stream_copy(src, dst, n_in, n_out, n):
+            calls.append(table["cfg"])
+
+    class FakeSrc:
+        dtype = "f32"
+
+    times = iter(range(100, 0, -1))
+    monkeypatch.setattr(bench, "time_calls", lambda fn, steps, warmup, torch, *a: (fn(), float(next(times)))[1])
+    ms, cfg = bench.copy_ceiling(None, FakeOps, FakeSrc(), None, 9, 10, 1000, 3)
+    assert table["cfg"] == {"block": 128}
+    last = bench.COPY_SHAPES[-1]
+    assert (cfg["block"], cfg["vector_bytes"], cfg["blocks_per_cu"]) == last and ms == 100 - len(bench.COPY_SHAPES) + 1
