@@ -137,14 +137,30 @@ PX_HD void two_sum(T a, T b, T& s, T& e) {
   e = (a - (s - bb)) + (b - bb);
 }
 
+// Error-free addition when |a| >= |b| (Dekker's FastTwoSum): a + b = s + e
+// exactly, in three operations instead of TwoSum's six.
+template <class T>
+PX_HD void fast_two_sum(T a, T b, T& s, T& e) {
+#if defined(__clang__)
+#pragma clang fp contract(off)
+#endif
+  s = a + b;
+  e = b - (s - a);
+}
+
 // Dot2 of (x1 y1 + x2 y2 + x3 y3).  The products' rounding errors (FMA)
 // and the additions' (TwoSum) are exact; only the two rounded additions
 // that gather them into the low word, t = q + r and s = s + t, lose
 // anything, each at most u times its rounded result (round to nearest).
 // rerr returns their running error sum |t1| + |s1| + |t2| + |s2|, so that
 // |hi + lo - exact| <= u * rerr.
-template <class T>
-PX_HD DW<T> dot3(T x1, T y1, T x2, T y2, T x3, T y3, T& rerr) {
+// ORDERED: the additions are FastTwoSums, exact only while the running sum
+// is at least as large in magnitude as the product added to it; `ordered`
+// is cleared where that fails (a diagonal cofactor of a positive-definite
+// matrix, x1 y1 - |.|^2 - |.|^2, passes its first test always; NaN fails).
+// Where it holds the result equals the TwoSum form's bit for bit.
+template <class T, bool ORDERED = false>
+PX_HD DW<T> dot3(T x1, T y1, T x2, T y2, T x3, T y3, T& rerr, bool* ordered = nullptr) {
 #if defined(__clang__)
 #pragma clang fp contract(off)
 #endif
@@ -153,25 +169,43 @@ PX_HD DW<T> dot3(T x1, T y1, T x2, T y2, T x3, T y3, T& rerr) {
   T h = x2 * y2;
   T r = fma_(x2, y2, -h);
   T q;
-  two_sum(p, h, p, q);
+  if constexpr (ORDERED) {
+    *ordered = *ordered && abs_(p) >= abs_(h);
+    fast_two_sum(p, h, p, q);
+  } else {
+    two_sum(p, h, p, q);
+  }
   T t = q + r;
   s = s + t;
   rerr = abs_(t) + abs_(s);
   h = x3 * y3;
   r = fma_(x3, y3, -h);
-  two_sum(p, h, p, q);
+  if constexpr (ORDERED) {
+    *ordered = *ordered && abs_(p) >= abs_(h);
+    fast_two_sum(p, h, p, q);
+  } else {
+    two_sum(p, h, p, q);
+  }
   t = q + r;
   s = s + t;
   rerr = rerr + (abs_(t) + abs_(s));
   return DW<T>{p, s};
 }
 
+// ordered (FP32 step only, null otherwise): the diagonal cofactors take the
+// FastTwoSum form and clear *ordered where its condition fails.
 template <class T>
-PX_HD void cofactors_comp(const T z[9], DW<T> c[9], T rerr[9]) {
+PX_HD void cofactors_comp(const T z[9], DW<T> c[9], T rerr[9], bool* ordered = nullptr) {
   const T a = z[0], d = z[1], f = z[2], br = z[3], bi = z[4], cr = z[5], ci = z[6], er = z[7], ei = z[8];
-  c[0] = dot3(d, f, -er, er, -ei, ei, rerr[0]);
-  c[1] = dot3(a, f, -cr, cr, -ci, ci, rerr[1]);
-  c[2] = dot3(a, d, -br, br, -bi, bi, rerr[2]);
+  if (ordered) {
+    c[0] = dot3<T, true>(d, f, -er, er, -ei, ei, rerr[0], ordered);
+    c[1] = dot3<T, true>(a, f, -cr, cr, -ci, ci, rerr[1], ordered);
+    c[2] = dot3<T, true>(a, d, -br, br, -bi, bi, rerr[2], ordered);
+  } else {
+    c[0] = dot3(d, f, -er, er, -ei, ei, rerr[0]);
+    c[1] = dot3(a, f, -cr, cr, -ci, ci, rerr[1]);
+    c[2] = dot3(a, d, -br, br, -bi, bi, rerr[2]);
+  }
   c[3] = dot3(cr, er, ci, ei, -br, f, rerr[3]);
   c[4] = dot3(ci, er, -cr, ei, -bi, f, rerr[4]);
   c[5] = dot3(br, er, -bi, ei, -cr, d, rerr[5]);
@@ -268,12 +302,13 @@ constexpr float REROUTE_REL = 1e-6f;
 PX_HD bool adjugate_comp_try(const float z[9], float x[9], float& det, float* bound_out = nullptr) {
   DW<float> c[9];
   float rerr[9], bound;
-  cofactors_comp(z, c, rerr);
+  bool ordered = true;
+  cofactors_comp(z, c, rerr, &ordered);
   det = det_comp(z, c, rerr, bound);
   if (bound_out) *bound_out = bound;
   const float t = 1.0f / det;
-  const bool ok = det > 0.0f && finite_(det) && finite_(t) && !(bound > REROUTE_REL * det) && z[0] > 0.0f &&
-                  c[2].hi + c[2].lo > 0.0f;
+  const bool ok = ordered && det > 0.0f && finite_(det) && finite_(t) && !(bound > REROUTE_REL * det) &&
+                  z[0] > 0.0f && c[2].hi + c[2].lo > 0.0f;
   scale_comp(c, t, x);
   return ok;
 }
