@@ -28,6 +28,10 @@ def lib():
         L.host_adjugate_comp_f64.restype = i64
         L.host_det_plain_bound_f32.argtypes = [i64, vp, i64, vp, vp, ctypes.c_int]
         L.host_det_plain_bound_f32.restype = None
+        L.host_sum_pair_f32.argtypes = [i64, vp, vp, vp, vp, ctypes.c_int]
+        L.host_sum_pair_f32.restype = None
+        L.host_diag_cofactors_f32.argtypes = [i64, vp, i64, vp, vp, vp]
+        L.host_diag_cofactors_f32.restype = None
         _L = L
     return _L
 
@@ -64,3 +68,21 @@ def det_plain_bound_f32(z):
     det, bound = np.empty(n, np.float32), np.empty(n, np.float32)
     lib().host_det_plain_bound_f32(n, _p(z), n, _p(det), _p(bound), _threads())
     return det, bound
+
+
+def sum_pair_f32(a, b, fast):
+    """(s, e) of the kernels' TwoSum (fast False) or FastTwoSum (fast True)."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    b = np.ascontiguousarray(b, dtype=np.float32)
+    s, e = np.empty_like(a), np.empty_like(a)
+    lib().host_sum_pair_f32(a.size, _p(a), _p(b), _p(s), _p(e), 1 if fast else 0)
+    return s, e
+
+
+def diag_cofactors_f32(z):
+    """The diagonal cofactors (hi, lo) of the FP32 step and its order flag."""
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.float32).reshape(9, -1))
+    n = z.shape[1]
+    hi, lo, ordered = np.empty((3, n), np.float32), np.empty((3, n), np.float32), np.empty(n, np.uint8)
+    lib().host_diag_cofactors_f32(n, _p(z), n, _p(hi), _p(lo), _p(ordered))
+    return hi, lo, ordered.astype(bool)

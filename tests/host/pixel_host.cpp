@@ -56,4 +56,27 @@ void host_det_plain_bound_f32(int64_t n, const float* z, int64_t zp, float* det,
   }
 }
 
+// The error-free additions of the compensated cofactors, element-wise:
+// TwoSum (kind 0) or FastTwoSum (kind 1).
+void host_sum_pair_f32(int64_t n, const float* a, const float* b, float* s, float* e, int kind) {
+  for (int64_t i = 0; i < n; ++i) {
+    if (kind) px::fast_two_sum(a[i], b[i], s[i], e[i]);
+    else px::two_sum(a[i], b[i], s[i], e[i]);
+  }
+}
+
+// The three diagonal cofactors in the ordered form, hi + lo, and the order
+// flag.
+void host_diag_cofactors_f32(int64_t n, const float* z, int64_t zp, float* hi, float* lo, uint8_t* ordered) {
+  for (int64_t i = 0; i < n; ++i) {
+    float zz[9], rerr[9];
+    for (int k = 0; k < 9; ++k) zz[k] = z[k * zp + i];
+    px::DW<float> c[9];
+    bool ord = true;
+    px::cofactors_comp(zz, c, rerr, &ord);
+    for (int k = 0; k < 3; ++k) { hi[k * n + i] = c[k].hi; lo[k * n + i] = c[k].lo; }
+    ordered[i] = ord ? 1 : 0;
+  }
+}
+
 }  // extern "C"

@@ -134,3 +134,59 @@ def test_plain_det_bound_covers_true_error():
     g8 = 8 * 2.0 ** -24 / (1 - 8 * 2.0 ** -24)
     planted = g8 * sum(np.abs(x) * np.abs(c) for x, c in zip(xs, cof))
     assert np.any(err > planted)
+
+
+def test_fast_two_sum_exact_when_ordered():
+    """FastTwoSum gives TwoSum's (s, e) bit for bit whenever |a| >= |b|, and
+    s + e equals a + b exactly (checked in rationals), over pairs spanning
+    the exponent range with opposite and equal signs."""
+    from fractions import Fraction
+    rng = np.random.default_rng(41)
+    m = 20000
+    a = (rng.standard_normal(m) * 10.0 ** rng.uniform(-20, 20, m)).astype(np.float32)
+    b = (rng.standard_normal(m) * np.abs(a) * 10.0 ** -rng.uniform(0, 12, m)).astype(np.float32)
+    b[:100] = -a[:100]                       # exact cancellation
+    b[100:200] = -np.nextafter(a[100:200], 0)  # near cancellation
+    swap = np.abs(b) > np.abs(a)
+    a[swap], b[swap] = b[swap], a[swap]
+    s0, e0 = pixel.sum_pair_f32(a, b, fast=False)
+    s1, e1 = pixel.sum_pair_f32(a, b, fast=True)
+    assert np.array_equal(s0.view(np.uint32), s1.view(np.uint32))
+    assert np.array_equal(e0.view(np.uint32), e1.view(np.uint32))
+    for i in rng.choice(m, 400, replace=False).tolist() + list(range(0, 200, 20)):
+        assert Fraction(float(s1[i])) + Fraction(float(e1[i])) == Fraction(float(a[i])) + Fraction(float(b[i]))
+    # out of order it is not error-free in general: the planted case must fail
+    s2, e2 = pixel.sum_pair_f32(np.float32([1e-8]), np.float32([1.0]), fast=True)
+    assert Fraction(float(s2[0])) + Fraction(float(e2[0])) != Fraction(float(np.float32(1e-8))) + 1
+
+
+def test_ordered_diagonal_cofactors():
+    """The diagonal cofactors' ordered form: on positive-definite matrices the
+    flag holds (hard ones up to kappa 1e10 included) and hi + lo is within the
+    Dot2 bound of the exact cofactor; a matrix whose lower 2x2 minor is
+    indefinite (|e|^2 > d f) clears the flag and is sent to the FP64 path,
+    which classifies it not positive definite."""
+    from fractions import Fraction
+    rng = np.random.default_rng(43)
+    z32 = hard(rng, 20000, 10.0).astype(np.float32)
+    pd = oracle.pd_class(z32.astype(np.float64)) == 0
+    hi, lo, ordered = pixel.diag_cofactors_f32(z32)
+    ordered_pd = ordered[pd]
+    # the first sum is always ordered for PD input; the second may fail only
+    # where the minor nearly vanishes, which the reroute absorbs
+    assert ordered_pd.mean() > 0.99
+    w = z32.astype(np.float64)
+    a, d, f, br, bi, cr, ci, er, ei = w
+    exact = [d * f - er * er - ei * ei, a * f - cr * cr - ci * ci, a * d - br * br - bi * bi]  # FP32 products exact in FP64
+    mags = [d * f + er * er + ei * ei, a * f + cr * cr + ci * ci, a * d + br * br + bi * bi]
+    u = 2.0 ** -24
+    for k in range(3):
+        idx = np.flatnonzero(pd & ordered)[:2000]
+        got = hi[k, idx].astype(np.float64) + lo[k, idx].astype(np.float64)
+        assert np.all(np.abs(got - exact[k][idx]) <= 4 * u * u * mags[k][idx] + 1e-300)
+    # an indefinite lower minor: er^2 > d f
+    bad = np.float32([[4.0], [1.0], [1.0], [0.1], [0.0], [0.1], [0.0], [2.0], [0.0]])
+    _, _, ordered_bad = pixel.diag_cofactors_f32(bad)
+    assert not ordered_bad[0]
+    _, _, st, _ = pixel.adjugate_comp_f32(bad)
+    assert st[0] == 2
