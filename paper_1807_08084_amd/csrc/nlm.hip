@@ -51,9 +51,13 @@ struct NlmArgs {
 };
 
 template <class T> __device__ __forceinline__ T exp2_(T x);
-template <> __device__ __forceinline__ float exp2_(float x) { return exp2f(x); }
+// FP32: the hardware's base-2 exponential (within 1 ulp; results below the
+// normal range flush, which only drops weights under 2^-126 of the largest)
+template <> __device__ __forceinline__ float exp2_(float x) { return __builtin_amdgcn_exp2f(x); }
 template <> __device__ __forceinline__ double exp2_(double x) { return exp2(x); }
 template <class T> __device__ __forceinline__ T log2_(T x);
+// (log2f, not the bare hardware logarithm: determinants of images with tiny
+// entries can be subnormal, which log2f scales first)
 template <> __device__ __forceinline__ float log2_(float x) { return log2f(x); }
 template <> __device__ __forceinline__ double log2_(double x) { return log2(x); }
 
@@ -151,9 +155,14 @@ __global__ __launch_bounds__(TW * LH) void k_nlm(NlmArgs a) {
         for (int k = 0; k < 9; ++k) q[k] = band[(k * TH + sl[m]) * BW + c];
         T s;
         if (DIST == 0) {
-          T tt = T(0);
+          // tr(Zp^-1 Zq) + tr(Zq^-1 Zp) as one chain of 18 FMAs
+          T tt = ip2[m][0] * q[0];
+          tt = fma(band[(9 * TH + sl[m]) * BW + c], zp2[m][0], tt);
 #pragma unroll
-          for (int k = 0; k < 9; ++k) tt += ip2[m][k] * q[k] + band[((9 + k) * TH + sl[m]) * BW + c] * zp2[m][k];
+          for (int k = 1; k < 9; ++k) {
+            tt = fma(ip2[m][k], q[k], tt);
+            tt = fma(band[((9 + k) * TH + sl[m]) * BW + c], zp2[m][k], tt);
+          }
           s = tt;
         } else {
           // det(Z_p + Z_q): the off-diagonal of zp2 is doubled, halve it back
