@@ -160,8 +160,8 @@ ROW_KERNELS = [
     ("k_boxcar_shift<float, 1, 1>", "boxcar 3x3 (halo rows: +2/32 of the reads)", 24, 40),
     ("k_boxcar_grouped<float, 1, 3>", "boxcar 7x7 (halo rows: +6/64 of the reads)", 24, 40),
     ("k_blockdiag<float, 1, 4, true>", "three-band block-diagonal inverse (27 planes in, 27 + det out)", 108, 112),
-    ("k_nlm<float, 0, 1>", "nonlocal means 23x23, KL (Z and its inverse in, filtered Z out)", 72, 36),
-    ("k_nlm<float, 1, 1>", "nonlocal means 23x23, Bhattacharyya (Z and det in)", 40, 36),
+    ("k_nlm<float, 0, 2>", "nonlocal means 23x23, KL (Z and its inverse in, filtered Z out)", 72, 36),
+    ("k_nlm<float, 1, 2>", "nonlocal means 23x23, Bhattacharyya (Z and det in)", 40, 36),
 ]
 
 
